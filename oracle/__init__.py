@@ -1,0 +1,111 @@
+"""CPU oracle for applying sequences of plane rotations (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does.
+
+Arrays follow the column-major convention of the C source: a logical
+``m x n`` matrix is a numpy array of shape ``(m, n)`` whose element (i, j)
+lives at ``base[i + j*ld]``, i.e. Fortran order with leading dimension ``ld``
+(``arr.strides == (8, 8*ld)``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load(path=None):
+    global _lib
+    if path is not None:
+        lib = ctypes.CDLL(path)
+    else:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+    i64, dp = ctypes.c_int64, ctypes.c_void_p
+    for name in ("oracle_rotseq_d", "oracle_rotseq_inverse_d"):
+        f = getattr(lib, name)
+        f.restype = None
+        f.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
+    f = lib.oracle_rotseq_threads_d
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int, i64, i64, i64, dp, i64, dp, i64, dp, i64]
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ld(arr, name):
+    """Leading dimension of a column-major float64 view; validates layout."""
+    if arr.dtype != np.float64:
+        raise TypeError(f"{name} must be float64 (got {arr.dtype})")
+    if arr.ndim != 2:
+        raise ValueError(f"{name} must be 2-D")
+    rows, cols = arr.shape
+    if rows == 0 or cols == 0:
+        return max(1, rows)
+    if arr.strides[0] != 8:
+        raise ValueError(f"{name} must be column-major (unit row stride)")
+    if cols == 1:
+        return max(1, rows)
+    ld = arr.strides[1] // 8
+    if ld < rows:
+        raise ValueError(f"{name}: leading dimension {ld} < rows {rows}")
+    return ld
+
+
+def _ptr(arr):
+    return arr.ctypes.data if arr.size else None
+
+
+def rotseq(A, C, S, *, lib=None, inverse=False, threads=None):
+    """Apply Algorithm 2 in place to the column-major float64 view ``A``.
+
+    ``A`` is m x n, ``C`` and ``S`` are (n-1) x k.  With ``inverse=True`` the
+    inverse sequence is applied instead (reverse order, transposed rotations).
+    ``threads`` > 1 splits the rows across host threads (bitwise identical).
+    Returns ``A``.
+    """
+    lib = lib or _load()
+    m, n = A.shape
+    nm1, k = C.shape
+    if S.shape != C.shape:
+        raise ValueError("C and S must have the same shape")
+    if n >= 1 and nm1 != max(n - 1, 0):
+        raise ValueError(f"C has {nm1} rows, expected n-1 = {n - 1}")
+    lda = _ld(A, "A")
+    ldc = _ld(C, "C")
+    lds = _ld(S, "S")
+    args = (m, n, k, _ptr(A), lda, _ptr(C), ldc, _ptr(S), lds)
+    if m == 0 or n <= 1 or k == 0:
+        return A
+    if inverse:
+        lib.oracle_rotseq_inverse_d(*args)
+    elif threads and threads > 1:
+        if lib.oracle_rotseq_threads_d(int(threads), *args) < 0:
+            raise RuntimeError("oracle thread start failed")
+    else:
+        lib.oracle_rotseq_d(*args)
+    return A
+
+
+def colmajor(arr, ld=None, fill=np.nan):
+    """Copy a 2-D array into a fresh column-major float64 buffer.
+
+    With ``ld`` > rows the padding rows of the buffer are set to ``fill`` so a
+    test can check that nothing outside the logical matrix is touched.
+    Returns the logical (rows x cols) view; ``view.base`` holds the buffer.
+    """
+    arr = np.asarray(arr, dtype=np.float64)
+    rows, cols = arr.shape
+    ld = max(1, rows) if ld is None else ld
+    buf = np.full((ld, max(cols, 1)), fill, dtype=np.float64, order="F")
+    buf[:rows, :cols] = arr
+    return buf[:rows, :cols]

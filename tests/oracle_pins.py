@@ -1,0 +1,297 @@
+"""Pins that tie the CPU oracle to facts fixed outside of it.
+
+Each pin takes ``apply(A, C, S, inverse=False)`` (an in-place rotation
+sequence on column-major float64 views) and raises AssertionError when the
+implementation disagrees with
+
+* brute force: the dense n x n product of the rotation matrices G(j, p)
+  (Algorithms 1 and 2 define A <- A G(0,0) ... G(n-2,k-1); G(j,p) is the
+  identity except G[j][j] = G[j+1][j+1] = c, G[j+1][j] = s, G[j][j+1] = -s),
+* exact rational arithmetic on the same floating-point inputs,
+* the reference BLAS routine drot (one sequence, k = 1),
+* closed forms (swap rotations, identity, reflection by -1, n = 2
+  composition) and the invariants of orthogonal transforms,
+* a hand-worked example stored under tests/golden/.
+
+The same pins are run against deliberately broken copies of the oracle
+(tests/test_oracle_mutants.py) to show that each plausible mistake is caught.
+"""
+from fractions import Fraction
+import math
+import os
+
+import numpy as np
+
+U = 2.0 ** -53  # unit roundoff of IEEE binary64
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def colmajor(arr, ld=None, fill=-999.5):
+    arr = np.asarray(arr, dtype=np.float64)
+    rows, cols = arr.shape
+    ld = max(1, rows) if ld is None else ld
+    buf = np.full((ld, max(cols, 1)), fill, dtype=np.float64, order="F")
+    buf[:rows, :cols] = arr
+    return buf[:rows, :cols]
+
+
+def rand_problem(rng, m, n, k, lda=None, ldc=None, lds=None):
+    A = colmajor(rng.standard_normal((m, n)), lda)
+    th = rng.uniform(0, 2 * math.pi, (max(n - 1, 0), k))
+    return A, colmajor(np.cos(th), ldc), colmajor(np.sin(th), lds)
+
+
+def dense_q(C, S, n):
+    """Q = prod_p prod_j G(j, p) in Algorithm 2's order, as a dense matrix."""
+    Q = np.eye(n)
+    nm1, k = C.shape
+    for p in range(k):
+        for j in range(nm1):
+            G = np.eye(n)
+            c, s = C[j, p], S[j, p]
+            G[j, j] = c
+            G[j + 1, j + 1] = c
+            G[j + 1, j] = s
+            G[j, j + 1] = -s
+            Q = Q @ G
+    return Q
+
+
+def relerr(X, Y):
+    den = np.linalg.norm(Y)
+    return np.linalg.norm(X - Y) / (den if den else 1.0)
+
+
+def _padding(A):
+    buf = A.base if A.base is not None else A
+    return buf[A.shape[0]:, :].copy()
+
+
+# ---------------------------------------------------------------- pins
+
+def pin_dense_bruteforce(apply):
+    """P-1: A G(0,0)...G(n-2,k-1) computed densely; also lda/ldc/lds padding."""
+    rng = np.random.Generator(np.random.PCG64(101))
+    cases = [(1, 2, 1), (3, 2, 4), (5, 3, 1), (4, 5, 3), (7, 8, 5), (8, 12, 4),
+             (6, 9, 9)]
+    for idx, (m, n, k) in enumerate(cases):
+        lda = m + (idx % 3)
+        ldc = n - 1 + (idx % 2)
+        lds = n - 1 + 2 * (idx % 2)
+        A, C, S = rand_problem(rng, m, n, k, lda, ldc, lds)
+        ref = np.asarray(A) @ dense_q(np.asarray(C), np.asarray(S), n)
+        pad = _padding(A)
+        apply(A, C, S)
+        e = relerr(A, ref)
+        assert e <= 1e-14, f"dense brute force m={m} n={n} k={k}: rel err {e:.3e}"
+        assert np.array_equal(_padding(A), pad), "padding rows of A were modified"
+
+
+def pin_inverse_dense(apply):
+    """The inverse applies Q^T: A Q^T computed densely."""
+    rng = np.random.Generator(np.random.PCG64(102))
+    for (m, n, k) in [(3, 4, 2), (5, 7, 3), (2, 2, 5)]:
+        A, C, S = rand_problem(rng, m, n, k, lda=m + 1)
+        ref = np.asarray(A) @ dense_q(np.asarray(C), np.asarray(S), n).T
+        apply(A, C, S, inverse=True)
+        e = relerr(A, ref)
+        assert e <= 1e-14, f"inverse vs dense m={m} n={n} k={k}: rel err {e:.3e}"
+
+
+def _frac_matmul(X, Y):
+    rows, inner, cols = len(X), len(Y), len(Y[0])
+    return [[sum((X[i][t] * Y[t][j] for t in range(inner)), Fraction(0))
+             for j in range(cols)] for i in range(rows)]
+
+
+def pin_exact_rational(apply):
+    """P-2: exact result of the same float inputs, via rational dense product.
+
+    Rounding bound used: every entry of a row takes part in at most 2k of the
+    (n-1)k rotations, each rotation commits at most 3u relative error per
+    output entry (two products and one sum), and orthogonal propagation does
+    not grow earlier errors, so ||row error|| <= 6 u (n-1) k ||row||.
+    """
+    # Pythagorean triples give well-conditioned rotations close to rationals.
+    triples = [(3, 4, 5), (5, 12, 13), (8, 15, 17), (7, 24, 25), (20, 21, 29)]
+    rng = np.random.Generator(np.random.PCG64(103))
+    m, n, k = 3, 6, 4
+    C = np.empty((n - 1, k))
+    S = np.empty((n - 1, k))
+    for p in range(k):
+        for j in range(n - 1):
+            a, b, h = triples[(j + 2 * p) % len(triples)]
+            sg = -1.0 if (j + p) % 3 == 0 else 1.0
+            C[j, p] = sg * a / h
+            S[j, p] = b / h if p % 2 == 0 else -b / h
+    A0 = rng.integers(-9, 10, (m, n)).astype(np.float64)
+    Qf = [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+    for p in range(k):
+        for j in range(n - 1):
+            G = [[Fraction(int(r == s)) for s in range(n)] for r in range(n)]
+            c, s = Fraction(C[j, p]), Fraction(S[j, p])
+            G[j][j] = c
+            G[j + 1][j + 1] = c
+            G[j + 1][j] = s
+            G[j][j + 1] = -s
+            Qf = _frac_matmul(Qf, G)
+    Af = [[Fraction(float(v)) for v in row] for row in A0]
+    exact = _frac_matmul(Af, Qf)
+    A = colmajor(A0)
+    apply(A, colmajor(C), colmajor(S))
+    for i in range(m):
+        err = math.sqrt(sum(float(Fraction(A[i, j]) - exact[i][j]) ** 2 for j in range(n)))
+        nrm = float(np.linalg.norm(A0[i]))
+        bound = 6 * U * (n - 1) * k * nrm
+        assert err <= bound, f"row {i}: error {err:.3e} above bound {bound:.3e}"
+
+
+def pin_drot(apply):
+    """P-3: one sequence equals the BLAS drot routine applied for j = 0..n-2."""
+    from scipy.linalg import blas
+    rng = np.random.Generator(np.random.PCG64(104))
+    m, n = 9, 7
+    A, C, S = rand_problem(rng, m, n, 1)
+    ref = np.array(A, dtype=np.float64, order="F")
+    for j in range(n - 1):
+        x, y = blas.drot(ref[:, j].copy(), ref[:, j + 1].copy(), C[j, 0], S[j, 0])
+        ref[:, j], ref[:, j + 1] = x, y
+    apply(A, C, S)
+    e = relerr(A, ref)
+    assert e <= 1e-15, f"drot comparison: rel err {e:.3e}"
+
+
+def pin_swap_closed_form(apply):
+    """P-4: c = 0, s = 1 shifts the columns left cyclically; the wrapped
+    column picks up the factor (-1)^(n-1).  Exact in binary64."""
+    rng = np.random.Generator(np.random.PCG64(105))
+    for (m, n, k) in [(4, 5, 3), (3, 6, 7), (2, 2, 3)]:
+        A0 = rng.standard_normal((m, n))
+        ref = A0.copy()
+        for _ in range(k):
+            first = ref[:, 0].copy()
+            ref[:, :-1] = ref[:, 1:]
+            ref[:, -1] = first * (-1.0) ** (n - 1)
+        A = colmajor(A0)
+        C = colmajor(np.zeros((n - 1, k)))
+        S = colmajor(np.ones((n - 1, k)))
+        apply(A, C, S)
+        assert np.array_equal(np.asarray(A), ref), f"swap closed form m={m} n={n} k={k}"
+
+
+def pin_n2_composition(apply):
+    """P-5: with n = 2 the k rotations compose into one rotation by sum(theta)."""
+    rng = np.random.Generator(np.random.PCG64(106))
+    m, k = 6, 9
+    th = rng.uniform(0, 2 * math.pi, k)
+    A0 = rng.standard_normal((m, 2))
+    T = float(np.sum(th))
+    c, s = math.cos(T), math.sin(T)
+    ref = np.stack([c * A0[:, 0] + s * A0[:, 1], -s * A0[:, 0] + c * A0[:, 1]], axis=1)
+    A = colmajor(A0)
+    apply(A, colmajor(np.cos(th)[None, :]), colmajor(np.sin(th)[None, :]))
+    e = relerr(A, ref)
+    assert e <= 20 * k * U, f"n=2 composition: rel err {e:.3e}"
+
+
+def pin_identity_and_reflection(apply):
+    """P-6: (c, s) = (1, 0) leaves A unchanged; (c, s) = (-1, 0) negates both
+    columns of every pair, so only columns 0 and n-1 change, by (-1)^k."""
+    rng = np.random.Generator(np.random.PCG64(107))
+    m, n, k = 5, 7, 3
+    A0 = rng.standard_normal((m, n))
+    A = colmajor(A0)
+    apply(A, colmajor(np.ones((n - 1, k))), colmajor(np.zeros((n - 1, k))))
+    assert np.array_equal(np.asarray(A), A0), "identity rotations changed A"
+    A = colmajor(A0)
+    apply(A, colmajor(-np.ones((n - 1, k))), colmajor(np.zeros((n - 1, k))))
+    ref = A0.copy()
+    ref[:, 0] *= (-1.0) ** k
+    ref[:, n - 1] *= (-1.0) ** k
+    assert np.array_equal(np.asarray(A), ref), "reflection closed form"
+
+
+def pin_norm_invariants(apply):
+    """P-7: orthogonal transforms keep every row's 2-norm."""
+    rng = np.random.Generator(np.random.PCG64(108))
+    m, n, k = 20, 33, 17
+    A, C, S = rand_problem(rng, m, n, k)
+    before = np.linalg.norm(np.asarray(A), axis=1)
+    apply(A, C, S)
+    after = np.linalg.norm(np.asarray(A), axis=1)
+    dev = np.max(np.abs(after - before) / before)
+    assert dev <= 6 * U * (n - 1) * k, f"row norm deviation {dev:.3e}"
+    assert relerr(np.asarray(A), np.zeros_like(np.asarray(A))) > 0
+
+
+def pin_round_trip(apply):
+    """P-8: the inverse sequence recovers A."""
+    rng = np.random.Generator(np.random.PCG64(109))
+    m, n, k = 11, 17, 6
+    A, C, S = rand_problem(rng, m, n, k, lda=13)
+    A0 = np.array(A)
+    apply(A, C, S)
+    assert relerr(A, A0) > 1e-3, "forward sequence did nothing"
+    apply(A, C, S, inverse=True)
+    e = relerr(A, A0)
+    assert e <= 12 * U * (n - 1) * k, f"round trip rel err {e:.3e}"
+
+
+def pin_row_independence(apply):
+    """P-9: permuting or subsetting rows permutes/subsets the output bitwise."""
+    rng = np.random.Generator(np.random.PCG64(110))
+    m, n, k = 12, 10, 5
+    A, C, S = rand_problem(rng, m, n, k)
+    A0 = np.array(A)
+    apply(A, C, S)
+    full = np.array(A)
+    perm = rng.permutation(m)
+    B = colmajor(A0[perm])
+    apply(B, C, S)
+    assert np.array_equal(np.asarray(B), full[perm]), "row permutation not bitwise"
+    sub = np.sort(rng.choice(m, 4, replace=False))
+    B = colmajor(A0[sub])
+    apply(B, C, S)
+    assert np.array_equal(np.asarray(B), full[sub]), "row subset not bitwise"
+
+
+def load_golden(name):
+    """Parse a golden fixture: 'key: v1 v2 ...' lines; '#' starts a comment."""
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, vals = line.split(":", 1)
+            out[key.strip()] = [Fraction(v) for v in vals.split()]
+    return out
+
+
+def pin_hand_worked(apply):
+    """A hand-worked example (tests/golden/hand_worked_rotseq.txt)."""
+    g = load_golden("hand_worked_rotseq.txt")
+    m, n, k = (int(v) for v in g["shape"])
+    A0 = np.array([float(v) for v in g["A"]]).reshape(n, m).T
+    C = np.array([float(v) for v in g["C"]]).reshape(k, n - 1).T
+    S = np.array([float(v) for v in g["S"]]).reshape(k, n - 1).T
+    ref = np.array([float(v) for v in g["result"]]).reshape(n, m).T
+    A = colmajor(A0)
+    apply(A, colmajor(C), colmajor(S))
+    e = relerr(A, ref)
+    assert e <= 8 * U * (n - 1) * k, f"hand-worked example: rel err {e:.3e}"
+
+
+ALL_PINS = [
+    pin_dense_bruteforce,
+    pin_inverse_dense,
+    pin_exact_rational,
+    pin_drot,
+    pin_swap_closed_form,
+    pin_n2_composition,
+    pin_identity_and_reflection,
+    pin_norm_invariants,
+    pin_round_trip,
+    pin_row_independence,
+    pin_hand_worked,
+]

@@ -1,0 +1,43 @@
+"""The CPU oracle against its pins (brute force, exact arithmetic, BLAS,
+closed forms, invariants, a hand-worked example).  CPU only."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle_pins import ALL_PINS, colmajor, rand_problem
+
+
+def oracle_apply(A, C, S, inverse=False):
+    oracle.rotseq(A, C, S, inverse=inverse)
+
+
+@pytest.mark.parametrize("pin", ALL_PINS, ids=lambda p: p.__name__)
+def test_pin(pin):
+    pin(oracle_apply)
+
+
+def test_threaded_driver_bitwise():
+    """Row-partitioned threads give the single-thread result bitwise."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    A, C, S = rand_problem(rng, 101, 40, 9, lda=103)
+    ref = np.array(A)
+    oracle.rotseq(colmajor(ref), C, S)
+    one = colmajor(np.array(A), 103)
+    oracle.rotseq(one, C, S)
+    for t in (2, 3, 8, 200):
+        B = colmajor(np.array(A), 103)
+        oracle.rotseq(B, C, S, threads=t)
+        assert np.array_equal(np.asarray(B), np.asarray(one))
+
+
+def test_quick_returns():
+    """m = 0, n <= 1 or k = 0 leave A untouched."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    A = colmajor(rng.standard_normal((4, 1)))
+    before = np.array(A)
+    oracle.rotseq(A, colmajor(np.zeros((0, 3))), colmajor(np.zeros((0, 3))))
+    assert np.array_equal(np.asarray(A), before)
+    A, C, S = rand_problem(rng, 4, 5, 0)
+    before = np.array(A)
+    oracle.rotseq(A, C, S)
+    assert np.array_equal(np.asarray(A), before)
