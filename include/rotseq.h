@@ -1,0 +1,172 @@
+/*
+ * librotseq: apply sequences of plane (Givens) rotations to a matrix on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Steel & Langou, "Communication efficient application of
+ * sequences of planar rotations to a matrix", Section 1, Algorithms 1 and 2):
+ * given an m x n matrix A and k sequences of n-1 rotations stored as cosine
+ * and sine matrices C and S of size (n-1) x k, overwrite A with
+ *
+ *     A <- A * G(0,0) G(1,0) ... G(n-2,0) G(0,1) ... G(n-2,k-1)
+ *
+ * where G(j,p) is the identity except in rows/columns j and j+1:
+ *     G[j][j] = G[j+1][j+1] = c,  G[j+1][j] = s,  G[j][j+1] = -s,
+ * with c = C(j,p), s = S(j,p).  Per row of A, rotation (j,p) does
+ *     x' = c*x + s*y,   y' = -s*x + c*y      (x = A(i,j), y = A(i,j+1)).
+ * Sequence p is applied after sequence p-1; within a sequence j ascends.
+ * The library applies the rotations in a reordered but dependency-preserving
+ * order (the wavefront of Section 1.1 and the blocks of Section 2), which
+ * gives the same result up to rounding.
+ *
+ * Storage: all matrices are column-major with a leading dimension:
+ *     A(i,j) = A[i + j*lda],  C(j,p) = C[j + p*ldc],  S(j,p) = S[j + p*lds].
+ *
+ * Pointers named "device" must be device memory of the current HIP device
+ * (hipMalloc, or a torch CUDA/HIP tensor's data pointer); they stay owned by
+ * the caller.  Calls are asynchronous and ordered on `stream` (0 = the null
+ * stream); device inputs must stay valid until the stream has passed the call.
+ * A must not overlap C, S or the workspace.  NaN or Inf inputs propagate.
+ *
+ * Return codes: 0 on success; -i if argument i (1-based) is invalid; a
+ * positive ROTSEQ_E_* code for runtime failures.  rotseq_strerror() names them.
+ */
+#ifndef ROTSEQ_H
+#define ROTSEQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ROTSEQ_SUCCESS        0
+#define ROTSEQ_E_HIP          1  /* a HIP runtime call failed                   */
+#define ROTSEQ_E_NOMEM        2  /* device workspace could not be allocated     */
+#define ROTSEQ_E_WORKSPACE    3  /* caller workspace too small or misaligned    */
+#define ROTSEQ_E_UNSUPPORTED  4  /* option combination not supported           */
+#define ROTSEQ_E_TIMEOUT      5  /* a device-side wait exceeded its spin limit  */
+
+/* Arithmetic used for one rotation (options.arith). */
+#define ROTSEQ_ARITH_AUTO   0  /* library choice (currently ROTSEQ_ARITH_LIFT) */
+/* Algorithm 1 exactly: two rounded products and one rounded sum per output,
+ * no fused multiply-add.  Bitwise equal to a plain loop of Algorithm 2. */
+#define ROTSEQ_ARITH_EXACT  1
+/* Algorithm 1 with fused multiply-adds: x' = fma(c,x,s*y), y' = fma(c,y,-s*x). */
+#define ROTSEQ_ARITH_FMA    2
+/* Three fused multiply-adds per entry (shear/lifting factorisation of the
+ * rotation, not from the paper):  x += a*y;  y += b*x;  x += a*y  with
+ * a = s/(1+c), b = -s for c >= 0.  Rotations with c < 0 are applied as
+ * (-c, -s) followed by negating both columns; the negations are tracked as
+ * column signs and undone when A is written back, so |a| <= 1 always. */
+#define ROTSEQ_ARITH_LIFT   3
+
+/* Kernel family (options.kernel). */
+#define ROTSEQ_KERNEL_AUTO      0
+/* One wave per 64-row tile sweeps all k sequences in passes of `band`
+ * sequences, reading and writing A once per pass. */
+#define ROTSEQ_KERNEL_MULTIPASS 1
+
+/*
+ * Tuning options; zero-initialise for library defaults.
+ *   arith   ROTSEQ_ARITH_*
+ *   kernel  ROTSEQ_KERNEL_*
+ *   band    sequences applied per wave per sweep over the columns
+ *           (the paper's k_b, Section 2); 0 = auto.  Must be one of
+ *           1, 2, 4, 8, 16 when given.
+ */
+typedef struct rotseq_opts {
+    int32_t arith;
+    int32_t kernel;
+    int32_t band;
+    int32_t reserved[5];
+} rotseq_opts;
+
+/*
+ * rotseq_d: FP64 rotation sequence, A <- A * prod G(j,p) (Algorithms 1-2).
+ *   1 m     rows of A, m >= 0
+ *   2 n     columns of A, n >= 0
+ *   3 k     number of rotation sequences, k >= 0
+ *   4 A     device, m x n, lda >= max(1,m); updated in place
+ *   5 lda   leading dimension of A
+ *   6 C     device, (n-1) x k cosines, ldc >= max(1,n-1)
+ *   7 ldc
+ *   8 S     device, (n-1) x k sines, lds >= max(1,n-1)
+ *   9 lds
+ *  10 stream
+ * Quick return (nothing is dereferenced) if m == 0, n <= 1 or k == 0.
+ * The library keeps one cached device workspace per (device, stream); use
+ * rotseq_ex_d with a caller workspace under HIP graph capture.
+ */
+int rotseq_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
+             const double *C, int64_t ldc, const double *S, int64_t lds,
+             hipStream_t stream);
+
+/* rotseq_s: FP32 version of rotseq_d, same arguments and semantics. */
+int rotseq_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
+             const float *C, int64_t ldc, const float *S, int64_t lds,
+             hipStream_t stream);
+
+/*
+ * rotseq_ex_d / rotseq_ex_s: as rotseq_d / rotseq_s with
+ *  11 opts        tuning options or NULL for defaults
+ *  12 workspace   device memory of at least rotseq_workspace_bytes(...)
+ *                 bytes, 256-byte aligned, or NULL to use the cached pool
+ *  13 ws_bytes    size of `workspace`
+ * With a caller workspace nothing is allocated, so the call can be captured
+ * into a HIP graph.  The workspace is in use until the stream passes the call.
+ */
+int rotseq_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
+                const double *C, int64_t ldc, const double *S, int64_t lds,
+                hipStream_t stream, const rotseq_opts *opts,
+                void *workspace, size_t ws_bytes);
+int rotseq_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
+                const float *C, int64_t ldc, const float *S, int64_t lds,
+                hipStream_t stream, const rotseq_opts *opts,
+                void *workspace, size_t ws_bytes);
+
+/*
+ * Device workspace bytes needed by rotseq_ex_{d,s} for this shape and
+ * options; dtype is 'd' or 's'.  Returns 0 for quick-return shapes and for
+ * invalid arguments.  Host-only; never touches the GPU.
+ */
+size_t rotseq_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k,
+                              const rotseq_opts *opts);
+
+/*
+ * Argument check of rotseq_d/rotseq_s without launching anything: returns 0
+ * or -i for the first invalid argument i as documented for rotseq_d.
+ * Host-only; pointers are only compared with NULL.
+ */
+int rotseq_check_args(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                      const void *C, int64_t ldc, const void *S, int64_t lds);
+
+/*
+ * Kernel timing for benchmarks.  While enabled, every call records HIP
+ * events on its own stream around the coefficient-preparation kernels and
+ * around the sweep kernel.  rotseq_profile_read waits for the recorded events
+ * (host-blocking), accumulates their durations into `out` and, if `reset` is
+ * nonzero, clears the totals.  Not for use under HIP graph capture.
+ */
+typedef struct rotseq_profile {
+    int64_t calls;        /* calls timed since the last reset            */
+    double prep_ms;       /* total time of the preparation kernels       */
+    double sweep_ms;      /* total time of the sweep kernel              */
+    double sweep_ms_min;  /* fastest single sweep                        */
+    double sweep_ms_max;  /* slowest single sweep                        */
+} rotseq_profile;
+int rotseq_profile_enable(int on);
+int rotseq_profile_read(rotseq_profile *out, int reset);
+
+/* Static description of a return code. */
+const char *rotseq_strerror(int code);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int rotseq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROTSEQ_H */

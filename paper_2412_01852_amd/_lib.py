@@ -1,0 +1,187 @@
+"""ctypes binding of librotseq's C ABI (argument marshalling only).
+
+Matrices are torch tensors on the HIP device in column-major layout: a
+logical m x n matrix is a 2-D tensor of shape (m, n) with strides (1, ld),
+ld >= m (``device_colmajor`` makes one).  Every computation runs in the HIP
+kernels of librotseq.so; there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librotseq.so")
+
+ARITH_AUTO, ARITH_EXACT, ARITH_FMA, ARITH_LIFT = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_MULTIPASS = 0, 1
+
+_lib = None
+
+
+class RotseqError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = f"librotseq error {code}: {strerror(code)}"
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("arith", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("band", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("prep_ms", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double), ("sweep_ms_min", ctypes.c_double),
+                ("sweep_ms_max", ctypes.c_double)]
+
+
+def profile_enable(on=True):
+    _load().rotseq_profile_enable(1 if on else 0)
+
+
+def profile_read(reset=False):
+    """Totals of the event-timed kernels since the last reset (waits for them)."""
+    out = Profile()
+    rc = _load().rotseq_profile_read(ctypes.byref(out), 1 if reset else 0)
+    if rc != 0:
+        raise RotseqError(rc, "profile_read")
+    return {f: getattr(out, f) for f, _ in Profile._fields_}
+
+
+def library_path():
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                           "`python -m paper_2412_01852_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, vp, i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+    base = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]
+    for name in ("rotseq_d", "rotseq_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, base
+    for name in ("rotseq_ex_d", "rotseq_ex_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, base + [ctypes.POINTER(Options), vp, ctypes.c_size_t]
+    lib.rotseq_workspace_bytes.restype = ctypes.c_size_t
+    lib.rotseq_workspace_bytes.argtypes = [ctypes.c_char, i64, i64, i64, ctypes.POINTER(Options)]
+    lib.rotseq_check_args.restype = i32
+    lib.rotseq_check_args.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64]
+    lib.rotseq_strerror.restype = ctypes.c_char_p
+    lib.rotseq_strerror.argtypes = [i32]
+    lib.rotseq_version.restype = i32
+    lib.rotseq_version.argtypes = []
+    lib.rotseq_profile_enable.restype = i32
+    lib.rotseq_profile_enable.argtypes = [i32]
+    lib.rotseq_profile_read.restype = i32
+    lib.rotseq_profile_read.argtypes = [ctypes.POINTER(Profile), i32]
+    _lib = lib
+    return lib
+
+
+def strerror(code):
+    return _load().rotseq_strerror(int(code)).decode()
+
+
+def version():
+    return _load().rotseq_version()
+
+
+def check_args(m, n, k, A, lda, C, ldc, S, lds):
+    """Host-only argument check (pointers are ints or None)."""
+    return _load().rotseq_check_args(m, n, k, A, lda, C, ldc, S, lds)
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, Options):
+        return ctypes.byref(opts)
+    o = Options()
+    for key, val in dict(opts).items():
+        setattr(o, key, int(val))
+    return ctypes.byref(o)
+
+
+def workspace_bytes(dtype, m, n, k, opts=None):
+    ch = {"float64": b"d", "double": b"d", "d": b"d", "float32": b"s", "float": b"s", "s": b"s"}[
+        str(dtype).replace("torch.", "")]
+    return _load().rotseq_workspace_bytes(ch, m, n, k, _opts(opts))
+
+
+def _ld(t, name):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    rows, cols = t.shape
+    if rows and cols and t.stride(0) != 1:
+        raise ValueError(f"{name} must be column-major (stride(0) == 1)")
+    if cols <= 1 or rows == 0:
+        return max(1, rows)
+    return t.stride(1)
+
+
+def rotseq(A, C, S, *, opts=None, workspace=None, stream=None):
+    """A <- A * G(0,0) ... G(n-2,k-1) in place on the GPU (Algorithms 1-2).
+
+    A: (m, n) float64/float32 column-major device tensor; C, S: (n-1, k) of the
+    same dtype.  ``opts`` is an Options or a dict of its fields; ``workspace``
+    an optional uint8 device tensor; ``stream`` a torch stream (default: the
+    current one).  Returns A.
+    """
+    import torch
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("A must be float64 or float32")
+    if C.dtype != A.dtype or S.dtype != A.dtype:
+        raise TypeError("A, C and S must share a dtype")
+    m, n = A.shape
+    k = C.shape[1]
+    if C.shape != S.shape or C.shape[0] != max(n - 1, 0):
+        raise ValueError(f"C and S must be ({max(n - 1, 0)}, k); got {tuple(C.shape)}, {tuple(S.shape)}")
+    for t, nm in ((A, "A"), (C, "C"), (S, "S")):
+        if t.numel() and not t.is_cuda:
+            raise ValueError(f"{nm} must be a device tensor")
+    lda, ldc, lds = _ld(A, "A"), _ld(C, "C"), _ld(S, "S")
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    handle = ctypes.c_void_p(st.cuda_stream)
+    ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    lib = _load()
+    dbl = A.dtype == torch.float64
+    if opts is None and workspace is None:
+        fn = lib.rotseq_d if dbl else lib.rotseq_s
+        rc = fn(m, n, k, ptr(A), lda, ptr(C), ldc, ptr(S), lds, handle)
+    else:
+        fn = lib.rotseq_ex_d if dbl else lib.rotseq_ex_s
+        wptr = workspace.data_ptr() if workspace is not None else None
+        wbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        rc = fn(m, n, k, ptr(A), lda, ptr(C), ldc, ptr(S), lds, handle, _opts(opts), wptr, wbytes)
+    if rc != 0:
+        raise RotseqError(rc, "rotseq")
+    return A
+
+
+def device_colmajor(view, device="cuda", dtype=None):
+    """Copy a column-major numpy view (with its padded buffer) to the device.
+
+    Returns an (m, n) tensor with strides (1, ld) over a device buffer holding
+    the whole ld x n host buffer, padding included.
+    """
+    import numpy as np
+    import torch
+    buf = view.base if view.base is not None else view
+    buf = np.asfortranarray(buf)
+    ld, cols = buf.shape
+    t = torch.from_numpy(np.ascontiguousarray(buf.T))  # (cols, ld), row j = column j
+    if dtype is not None:
+        t = t.to(dtype)
+    t = t.to(device)
+    return t.t()[: view.shape[0], : view.shape[1]]
+
+
+def host_colmajor(t):
+    """Device column-major (m, n) tensor -> numpy float64 (m, n) array."""
+    return t.detach().to("cpu", dtype=__import__("torch").float64).numpy()

@@ -1,0 +1,382 @@
+// HIP kernels of librotseq for gfx950 (CDNA4, wave64).
+//
+// Operation: A <- A * G(0,0) ... G(n-2,k-1) (Algorithms 1 and 2 of the
+// paper).  Rows of A are independent, so one 64-lane wave owns a 64-row tile
+// of A (one row per lane) and never talks to other waves.  Inside a tile the
+// rotations are applied in the wavefront order of Section 1.1: step t of a
+// band of K sequences (p0 .. p0+K-1) applies the rotations
+//     (j = t - q, p = p0 + q)   for q = 0, 1, ..., K-1   (in that order),
+// which respects the only ordering constraint of Algorithm 2 (rotation (j,p)
+// after (j+1,p-1) and after (j-1,p)) and touches the K+1 columns t-K+1..t+1.
+// Those columns live in a register ring; each step loads one new column
+// (t+1+D, D steps ahead) and stores one finished column (t-K+1), so A is read
+// and written once per band instead of once per sequence (Sections 1.1-3).
+// The startup and shutdown triangles of every band (Section 2) are padded
+// with identity rotations and virtual zero columns, so every step runs the
+// same straight-line code.
+//
+// The coefficients of step t form one contiguous record of K pairs, prepared
+// by prep_coef in the order the sweep consumes them (the paper's "packing of
+// C and S", Section 4).  They are identical for all 64 lanes, so the sweep
+// reads them through the scalar data cache into SGPRs (one SGPR-pair operand
+// per FMA) instead of broadcasting through LDS or vector registers.
+//
+// Edges use buffer descriptors: a column descriptor covers exactly the valid
+// rows of the tile (fewer than 64 in the last tile), and columns outside
+// [0, n) get an empty descriptor, so out-of-range loads return 0 and
+// out-of-range stores are dropped by the hardware without a branch.
+#include <hip/hip_runtime.h>
+
+#include "rotseq_internal.h"
+
+namespace rotseq {
+namespace {
+
+constexpr int kWave = 64;
+// Dword 3 of a gfx9-family buffer descriptor: 32-bit data format, no swizzle.
+constexpr int kRsrcWord3 = 0x00020000;
+// Cache policy for loads of A: SC0 set, i.e. served coherently from L2 (the
+// CU's L1 may hold a stale copy of a column written by the previous band).
+constexpr int kLoadCoherent = 1;
+// Wavefront steps a column load is issued ahead of its first use.
+constexpr int kPrefetch = 4;
+
+template <typename T>
+struct CoefPair {
+    T a, b;
+};
+
+// Address space 4 (constant): uniform loads through these pointers become
+// scalar loads into SGPRs.
+template <typename T>
+using ConstPairs = const __attribute__((address_space(4))) CoefPair<T> *;
+template <typename T>
+using ConstScalars = const __attribute__((address_space(4))) T *;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, kRsrcWord3);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double buf_load(double, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, kLoadCoherent);
+    return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ float buf_load(float, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, kLoadCoherent);
+    return __builtin_bit_cast(float, v);
+}
+__device__ __forceinline__ void buf_store(double x, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, 0, 0);
+}
+__device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, 0, 0);
+}
+
+// Keeps a running scalar address opaque to loop strength reduction, which
+// would otherwise turn each unrolled step's address into its own 64-bit
+// induction variable and exhaust the SGPR file.  Emits no instruction.
+__device__ __forceinline__ void opaque(uint64_t &x) { asm volatile("" : "+s"(x)); }
+
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// One rotation of the entries (x, y) of a row; (a, b) as prepared by prep_coef.
+template <int ARITH, typename T>
+__device__ __forceinline__ void rotate(T &x, T &y, T a, T b)
+{
+    if constexpr (ARITH == kExact) {
+        // Algorithm 1 as written: (a, b) = (c, s), every product and sum
+        // rounded separately.
+#pragma clang fp contract(off)
+        T t = a * x + b * y;
+        y = -b * x + a * y;
+        x = t;
+    } else if constexpr (ARITH == kFma) {
+        T t = fmad(a, x, b * y);
+        y = fmad(a, y, -(b * x));
+        x = t;
+    } else {
+        // Lifting form, (a, b) = (s'/(1+c'), -s') with c' >= 0.
+        x = fmad(a, y, x);
+        y = fmad(b, x, y);
+        x = fmad(a, y, x);
+    }
+}
+
+// One band of K sequences over the whole tile: steps t = 0 .. steps-1.
+// `tile` is the address of A(i0, 0), `ldab` the column stride in bytes.
+template <typename T, int K, int ARITH, bool SIGN>
+__device__ __forceinline__ void sweep_band(uint64_t tile, uint64_t ldab, uint32_t rowbytes, int voff,
+                                           int n, ConstPairs<T> w, int steps, ConstScalars<T> sign)
+{
+    constexpr int D = kPrefetch;
+    constexpr int R = K + 1 + D;  // ring: K+1 live columns + D in flight
+    T ring[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+        ring[s] = T(0);
+    // Load stream: column lc at address lp.  Store stream: column sc at sp.
+    uint64_t lp = tile;
+    int lc = 0;
+#pragma unroll
+    for (int c = 0; c <= D; ++c) {
+        ring[c] = buf_load(T(), make_rsrc((const void *)lp, lc < n ? rowbytes : 0u), voff);
+        lp += ldab;
+        ++lc;
+        opaque(lp);
+    }
+    uint64_t sp = tile - (uint64_t)(K - 1) * ldab;
+    int sc = -(K - 1);
+    uint64_t wp = (uint64_t)w;
+
+    for (int t0 = 0; t0 < steps; t0 += R) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            // Column t+1+D goes into the slot of column t-K, stored last step.
+            ring[(u + D + 1) % R] =
+                buf_load(T(), make_rsrc((const void *)lp, lc < n ? rowbytes : 0u), voff);
+            lp += ldab;
+            ++lc;
+            opaque(lp);
+            ConstPairs<T> wt = (ConstPairs<T>)wp;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const T a = wt[q].a, b = wt[q].b;
+                rotate<ARITH>(ring[(u - q + R) % R], ring[(u - q + 1 + R) % R], a, b);
+            }
+            wp += K * sizeof(CoefPair<T>);
+            opaque(wp);
+            // Column t-K+1 has seen all K sequences of the band.
+            T v = ring[(u - K + 1 + R) % R];
+            const bool valid = (unsigned)sc < (unsigned)n;
+            if constexpr (SIGN)
+                v *= sign[valid ? sc : 0];
+            buf_store(v, make_rsrc((const void *)sp, valid ? rowbytes : 0u), voff);
+            sp += ldab;
+            ++sc;
+            opaque(sp);
+            // Keep the scheduler from hoisting the scalar coefficient loads of
+            // later steps: they would exhaust the SGPR file and spill.
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Multi-pass sweep: one wave per 64-row tile applies the bands one after the
+// other; A round-trips through memory between bands.
+template <typename T, int K, int ARITH>
+__global__ __launch_bounds__(kWave) void sweep_multipass(T *__restrict__ A, int64_t lda, int64_t m,
+                                                         int64_t n,
+                                                         const CoefPair<T> *__restrict__ coef,
+                                                         int steps, int npass,
+                                                         const T *__restrict__ sign)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * kWave;
+    const int64_t rows = m - i0 < kWave ? m - i0 : kWave;
+    const uint32_t rowbytes = (uint32_t)(rows * (int64_t)sizeof(T));
+    const int voff = threadIdx.x * (int)sizeof(T);
+    const uint64_t tile = (uint64_t)(A + i0);
+    const uint64_t ldab = (uint64_t)lda * sizeof(T);
+    for (int pass = 0; pass < npass; ++pass) {
+        ConstPairs<T> w = (ConstPairs<T>)(coef + (int64_t)pass * steps * K);
+        if (ARITH == kLift && pass == npass - 1)
+            sweep_band<T, K, ARITH, true>(tile, ldab, rowbytes, voff, (int)n, w, steps,
+                                          (ConstScalars<T>)sign);
+        else
+            sweep_band<T, K, ARITH, false>(tile, ldab, rowbytes, voff, (int)n, w, steps,
+                                           (ConstScalars<T>)sign);
+        // The next band re-reads the columns this band stored.
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+}
+
+// ------------------------------------------------------------------ prep
+//
+// Column signs of the lifting form: a rotation with c < 0 is applied as
+// (-c, -s) and leaves both of its columns negated.  neg(j,p) = [C(j,p) < 0]
+// is known up front, so the sign of column j just before rotation (j,p) in
+// Algorithm 2's order is the parity of neg over the rotations that touched it
+// earlier: (j-1, p') for p' <= p and (j, p') for p' < p.  A rotation sees its
+// columns' signs only through their product, which turns s into
+// s' = s * sign(j) * sign(j+1).
+
+__device__ __forceinline__ uint64_t low_bits(int q) { return q >= 64 ? ~0ull : ((1ull << q) - 1); }
+
+// negmask[pass*(n-1) + j] bit q = [C(j, pass*K + q) < 0].
+template <typename T>
+__global__ void prep_negmask(const T *__restrict__ C, int64_t ldc, int64_t n1, int64_t k, int K,
+                             int npass, uint64_t *__restrict__ negmask)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npass * n1)
+        return;
+    const int64_t pass = idx / n1, j = idx - pass * n1;
+    uint64_t mask = 0;
+    for (int q = 0; q < K; ++q) {
+        const int64_t p = pass * K + q;
+        if (p < k && C[j + p * ldc] < T(0))
+            mask |= 1ull << q;
+    }
+    negmask[idx] = mask;
+}
+
+// parity[pass*(n-1) + j] = parity of the negations by pair j in bands < pass,
+// for pass = 0 .. npass (the last row is the total).
+__global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
+                            uint8_t *__restrict__ parity)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n1)
+        return;
+    unsigned acc = 0;
+    for (int pass = 0; pass < npass; ++pass) {
+        parity[(int64_t)pass * n1 + j] = (uint8_t)acc;
+        acc ^= __builtin_popcountll(negmask[(int64_t)pass * n1 + j]) & 1u;
+    }
+    parity[(int64_t)npass * n1 + j] = (uint8_t)acc;
+}
+
+// sign[c] = (-1)^(negations of column c by pairs c-1 and c over all bands).
+template <typename T>
+__global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__restrict__ sign)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n)
+        return;
+    const unsigned f = (c > 0 ? total[c - 1] : 0u) ^ (c + 1 < n ? total[c] : 0u);
+    sign[c] = f ? T(-1) : T(1);
+}
+
+// coef[(pass*steps + t)*K + q] = coefficients of rotation (t-q, pass*K+q),
+// or the identity where that rotation does not exist.
+template <typename T>
+__global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S,
+                          int64_t lds, int64_t n1, int64_t k, int K, int steps, int npass,
+                          int arith, const uint64_t *__restrict__ negmask,
+                          const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)npass * steps * K;
+    if (idx >= total)
+        return;
+    const int q = (int)(idx % K);
+    const int64_t t = (idx / K) % steps;
+    const int64_t pass = idx / ((int64_t)K * steps);
+    const int64_t j = t - q, p = pass * K + q;
+    CoefPair<T> out;
+    if (j >= 0 && j < n1 && p < k) {
+        const T c = C[j + p * ldc], s = S[j + p * lds];
+        if (arith == kLift) {
+            const uint64_t *nm = negmask + pass * n1;
+            const uint8_t *par = parity + pass * n1;
+            unsigned tau = 0;
+            if (j > 0)
+                tau ^= par[j - 1] ^ (__builtin_popcountll(nm[j - 1] & low_bits(q + 1)) & 1u);
+            if (j + 1 < n1)
+                tau ^= par[j + 1] ^ (__builtin_popcountll(nm[j + 1] & low_bits(q)) & 1u);
+            const double cd = (double)c;
+            const double sd = tau ? -(double)s : (double)s;
+            double a, b;
+            if (!(cd < 0.0)) {
+                a = sd / (1.0 + cd);
+                b = -sd;
+            } else {
+                a = -sd / (1.0 - cd);
+                b = sd;
+            }
+            out.a = (T)a;
+            out.b = (T)b;
+        } else {
+            out.a = c;
+            out.b = s;
+        }
+    } else {
+        out.a = arith == kLift ? T(0) : T(1);
+        out.b = T(0);
+    }
+    coef[idx] = out;
+}
+
+inline unsigned blocks_for(int64_t count, int threads) { return (unsigned)((count + threads - 1) / threads); }
+
+template <typename T>
+hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t st)
+{
+    const int64_t n1 = p.n - 1;
+    uint64_t *negmask = (uint64_t *)(ws + p.off_negmask);
+    uint8_t *parity = (uint8_t *)(ws + p.off_parity);
+    T *sign = (T *)(ws + p.off_sign);
+    CoefPair<T> *coef = (CoefPair<T> *)(ws + p.off_coef);
+    constexpr int B = 256;
+    if (p.arith == kLift) {
+        prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(C, p.ldc, n1, p.k, p.band,
+                                                                          p.npass, negmask);
+        prep_parity<<<blocks_for(n1, B), B, 0, st>>>(negmask, n1, p.npass, parity);
+        prep_sign<T><<<blocks_for(p.n, B), B, 0, st>>>(parity + (int64_t)p.npass * n1, p.n, sign);
+    }
+    const int64_t total = (int64_t)p.npass * p.steps * p.band;
+    prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.ldc, S, p.lds, n1, p.k, p.band, p.steps,
+                                                    p.npass, p.arith, negmask, parity, coef);
+    return hipGetLastError();
+}
+
+template <typename T, int K, int ARITH>
+hipError_t go_multipass(const Plan &p, T *A, const char *ws, hipStream_t st)
+{
+    const unsigned tiles = (unsigned)((p.m + kWave - 1) / kWave);
+    sweep_multipass<T, K, ARITH><<<tiles, kWave, 0, st>>>(
+        A, p.lda, p.m, p.n, (const CoefPair<T> *)(ws + p.off_coef), p.steps, p.npass,
+        (const T *)(ws + p.off_sign));
+    return hipGetLastError();
+}
+
+template <typename T, int ARITH>
+hipError_t sweep_arith(const Plan &p, T *A, const char *ws, hipStream_t st)
+{
+    switch (p.band) {
+    case 1: return go_multipass<T, 1, ARITH>(p, A, ws, st);
+    case 2: return go_multipass<T, 2, ARITH>(p, A, ws, st);
+    case 4: return go_multipass<T, 4, ARITH>(p, A, ws, st);
+    case 8: return go_multipass<T, 8, ARITH>(p, A, ws, st);
+    case 16: return go_multipass<T, 16, ARITH>(p, A, ws, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t sweep_t(const Plan &p, T *A, const char *ws, hipStream_t st)
+{
+    switch (p.arith) {
+    case kExact: return sweep_arith<T, kExact>(p, A, ws, st);
+    case kFma: return sweep_arith<T, kFma>(p, A, ws, st);
+    case kLift: return sweep_arith<T, kLift>(p, A, ws, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int unroll_for_band(int band) { return band + 1 + kPrefetch; }
+
+hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t stream)
+{
+    if (p.esize == 8)
+        return prep_t<double>(p, (const double *)C, (const double *)S, (char *)ws, stream);
+    return prep_t<float>(p, (const float *)C, (const float *)S, (char *)ws, stream);
+}
+
+hipError_t launch_sweep(const Plan &p, void *A, const void *ws, hipStream_t stream)
+{
+    if (p.esize == 8)
+        return sweep_t<double>(p, (double *)A, (const char *)ws, stream);
+    return sweep_t<float>(p, (float *)A, (const char *)ws, stream);
+}
+
+}  // namespace rotseq

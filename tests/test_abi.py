@@ -1,0 +1,83 @@
+"""C-ABI library: loads, exports every declared symbol, validates arguments.
+CPU only: nothing here launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2412_01852_amd as rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"#[^\n]*", "", text)
+        for m in re.finditer(r"\b([a-z_][a-z0-9_]*)\s*\(", text):
+            name = m.group(1)
+            prefix = text[max(0, m.start() - 80): m.start()]
+            if name.startswith("rotseq_") and not re.search(r"typedef[^;]*$", prefix):
+                names.append(name)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(rs.library_path())
+    names = declared_functions()
+    assert "rotseq_d" in names and "rotseq_s" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_version_and_strerror():
+    assert rs.version() >= 100
+    assert rs.strerror(0) == "success"
+    assert "invalid argument" in rs.strerror(-4)
+    for code in range(1, 6):
+        assert rs.strerror(code) != "unknown error code"
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((4, 5, 6, 1, 4, 1, 4, 1, 4), 0),
+    ((-1, 5, 6, 1, 4, 1, 4, 1, 4), -1),
+    ((4, -5, 6, 1, 4, 1, 4, 1, 4), -2),
+    ((4, 5, -6, 1, 4, 1, 4, 1, 4), -3),
+    ((4, 5, 6, None, 4, 1, 4, 1, 4), -4),
+    ((4, 5, 6, 1, 3, 1, 4, 1, 4), -5),
+    ((4, 5, 6, 1, 4, None, 4, 1, 4), -6),
+    ((4, 5, 6, 1, 4, 1, 3, 1, 4), -7),
+    ((4, 5, 6, 1, 4, 1, 4, None, 4), -8),
+    ((4, 5, 6, 1, 4, 1, 4, 1, 3), -9),
+    # quick-return shapes accept NULL pointers but still check leading dims
+    ((0, 5, 6, None, 1, None, 4, None, 4), 0),
+    ((4, 1, 6, None, 4, None, 1, None, 1), 0),
+    ((4, 5, 0, None, 4, None, 4, None, 4), 0),
+    ((0, 0, 0, None, 0, None, 0, None, 0), -5),
+    ((0, 0, 0, None, 1, None, 1, None, 0), -9),
+    ((3, 1, 2, None, 3, None, 0, None, 1), -7),
+])
+def test_check_args(args, expect):
+    assert rs.check_args(*args) == expect
+
+
+def test_workspace_bytes():
+    assert rs.workspace_bytes("float64", 0, 5, 6) == 0
+    assert rs.workspace_bytes("float64", 5, 1, 6) == 0
+    assert rs.workspace_bytes("float64", 5, 5, 0) == 0
+    a = rs.workspace_bytes("float64", 64, 100, 16)
+    b = rs.workspace_bytes("float32", 64, 100, 16)
+    assert a > b > 0
+    assert a % 256 == 0
+    # bands of 16: 12 passes over (n + 15 padded to 21) steps of 16 pairs
+    big = rs.workspace_bytes("float64", 10240, 10240, 192)
+    assert big >= 12 * 10255 * 16 * 16
+    assert rs.workspace_bytes("float64", 64, 100, 16, {"band": 3}) == 0
+    assert rs.workspace_bytes("float64", 64, 100, 16, {"arith": 9}) == 0

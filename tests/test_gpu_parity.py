@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: relative Frobenius error ||A_gpu - A_ref|| / ||A_in|| <= 1e-13 (FP64)
+and <= 5e-6 (FP32, oracle in FP64 on the widened FP32 inputs); the exact
+arithmetic mode (Algorithm 1 without fused multiply-adds) must be bitwise.
+Large shapes are checked on sampled rows, which the oracle computes alone
+because rows of A never interact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2412_01852_amd as rs
+from paper_2412_01852_amd.inputs import make_problem
+from gpu_util import TOL, oracle_rows, padding_bits, relerr, say, to_dev, widened
+
+pytestmark = pytest.mark.gpu
+
+ARITHS = {"exact": rs.ARITH_EXACT, "fma": rs.ARITH_FMA, "lift": rs.ARITH_LIFT}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def run_full(pb, dtype, opts=None):
+    """Whole-matrix run; returns (gpu result, oracle result, padding ok)."""
+    import torch
+    A = to_dev(pb.A, dtype)
+    C = to_dev(pb.C, dtype)
+    S = to_dev(pb.S, dtype)
+    pad_before = padding_bits(A)
+    rs.rotseq(A, C, S, opts=opts)
+    torch.cuda.synchronize()
+    got = rs.host_colmajor(A)
+    ref = oracle.colmajor(widened(pb.A, dtype))
+    oracle.rotseq(ref, oracle.colmajor(widened(pb.C, dtype)), oracle.colmajor(widened(pb.S, dtype)))
+    return got, np.asarray(ref), np.array_equal(pad_before, padding_bits(A))
+
+
+@pytest.mark.parametrize("arith", sorted(ARITHS))
+def test_plain_512_fp64(arith):
+    """m = n = 512, k = 32 (the small plain configuration)."""
+    say(f"plain 512x512 k=32 fp64 arith={arith}")
+    pb = make_problem(512, 512, 32, seed=1)
+    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith]})
+    assert pad_ok
+    if arith == "exact":
+        assert np.array_equal(got, ref), "exact mode must be bitwise equal to the oracle"
+    else:
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+
+
+EDGE = [
+    # m, n, k, lda pad, ldc pad, lds pad
+    (1, 2, 1, 0, 0, 0), (63, 3, 2, 1, 0, 2), (65, 2, 5, 3, 1, 0), (64, 64, 64, 0, 0, 0),
+    (130, 17, 33, 2, 3, 1), (100, 5, 20, 0, 0, 0), (70, 40, 17, 6, 0, 0), (1, 300, 3, 0, 0, 0),
+    (129, 1, 5, 0, 0, 0), (0, 7, 3, 0, 0, 0), (7, 7, 0, 0, 0, 0), (7, 0, 3, 0, 0, 0),
+    (200, 2, 1, 0, 0, 0), (3, 129, 128, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("m,n,k,pa,pc,ps", EDGE)
+@pytest.mark.parametrize("arith", ["exact", "lift"])
+def test_edges_fp64(m, n, k, pa, pc, ps, arith):
+    say(f"edge fp64 m={m} n={n} k={k} pads={pa},{pc},{ps} arith={arith}")
+    pb = make_problem(m, n, k, seed=m + 7 * n + 13 * k,
+                      lda=max(1, m) + pa, ldc=max(1, n - 1) + pc, lds=max(1, n - 1) + ps)
+    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith]})
+    assert pad_ok, "padding rows of A were modified"
+    if arith == "exact":
+        assert np.array_equal(got, ref)
+    else:
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("band", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("arith", sorted(ARITHS))
+def test_bands_fp64(band, arith):
+    say(f"bands fp64 band={band} arith={arith}")
+    pb = make_problem(200, 300, 37, seed=band)
+    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith], "band": band})
+    if arith == "exact":
+        assert np.array_equal(got, ref)
+    else:
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("m,n,k", [(512, 512, 32), (65, 40, 17), (1, 2, 1), (130, 17, 33)])
+@pytest.mark.parametrize("arith", sorted(ARITHS))
+def test_fp32(m, n, k, arith):
+    say(f"fp32 m={m} n={n} k={k} arith={arith}")
+    pb = make_problem(m, n, k, seed=3 + m)
+    got, ref, pad_ok = run_full(pb, "f32", {"arith": ARITHS[arith]})
+    assert pad_ok
+    assert relerr(got, ref, widened(pb.A, "f32")) <= TOL["f32"]
+
+
+def sample_rows(m, rng, extra=24):
+    fixed = {0, 1, 62, 63, 64, 65, m // 2, m - 65, m - 64, m - 1}
+    rows = sorted({r for r in fixed if 0 <= r < m} | set(rng.choice(m, extra, replace=False).tolist()))
+    return np.asarray(rows)
+
+
+def run_sampled(m, n, k, seed, dtype, opts=None):
+    import torch
+    pb = make_problem(m, n, k, seed=seed)
+    A = to_dev(pb.A, dtype)
+    C = to_dev(pb.C, dtype)
+    S = to_dev(pb.S, dtype)
+    norms0 = torch.linalg.vector_norm(A.double(), dim=1)
+    rs.rotseq(A, C, S, opts=opts)
+    torch.cuda.synchronize()
+    norms1 = torch.linalg.vector_norm(A.double(), dim=1)
+    rows = sample_rows(m, np.random.Generator(np.random.PCG64(seed)))
+    got = A[torch.as_tensor(rows, device=A.device)].double().cpu().numpy()
+    ref = oracle_rows(pb.A, pb.C, pb.S, rows, dtype)
+    a0 = widened(pb.A, dtype)[rows]
+    drift = float(torch.max(torch.abs(norms1 - norms0) / norms0))
+    return relerr(got, ref, a0), drift
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_target_10240_k192_sampled(dtype):
+    """m = n = 10240, k = 192: sampled rows against the oracle; every row's
+    norm is preserved (an orthogonal transform)."""
+    say(f"target 10240x10240 k=192 {dtype} (sampled rows)")
+    err, drift = run_sampled(10240, 10240, 192, 2, dtype)
+    say(f"  rel err {err:.3e}  max row-norm drift {drift:.3e}")
+    assert err <= TOL[dtype]
+    assert drift <= (1e-12 if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("k", [1, 8, 32, 128])
+def test_tall_32768x4096_sampled(k):
+    say(f"tall 32768x4096 k={k} fp64 (sampled rows)")
+    err, drift = run_sampled(32768, 4096, k, 3 + k, "f64")
+    say(f"  rel err {err:.3e}")
+    assert err <= TOL["f64"]
+
+
+def test_caller_workspace_and_stream():
+    """rotseq_ex_d with a caller workspace on a side stream equals the pooled call."""
+    import torch
+    say("caller workspace + side stream")
+    pb = make_problem(300, 257, 40, seed=9)
+    A1, C, S = to_dev(pb.A, "f64"), to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    A2 = to_dev(pb.A, "f64")
+    rs.rotseq(A1, C, S)
+    nbytes = rs.workspace_bytes("float64", 300, 257, 40)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rs.rotseq(A2, C, S, opts={"arith": 0}, workspace=ws, stream=side)
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(A1, A2)
+    with pytest.raises(rs.RotseqError):
+        rs.rotseq(A2, C, S, opts={}, workspace=ws[: nbytes // 2])
+
+
+def test_repeated_calls_reuse_pool():
+    """Back-to-back calls of growing and shrinking size through the pool."""
+    import torch
+    say("repeated calls")
+    for (m, n, k) in [(64, 50, 3), (256, 700, 70), (64, 50, 3), (1000, 33, 5)]:
+        pb = make_problem(m, n, k, seed=m + n + k)
+        got, ref, _ = run_full(pb, "f64")
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+    torch.cuda.synchronize()
