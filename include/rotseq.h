@@ -67,20 +67,30 @@ extern "C" {
 /* One wave per 64-row tile sweeps all k sequences in passes of `band`
  * sequences, reading and writing A once per pass. */
 #define ROTSEQ_KERNEL_MULTIPASS 1
+/* Chains of (tile, band) waves: consecutive bands of a tile hand columns to
+ * each other through LDS inside a workgroup and through A (with device-scope
+ * progress counters) across workgroups; one workgroup per CU.  Default. */
+#define ROTSEQ_KERNEL_CHAIN     2
 
 /*
  * Tuning options; zero-initialise for library defaults.
  *   arith   ROTSEQ_ARITH_*
  *   kernel  ROTSEQ_KERNEL_*
  *   band    sequences applied per wave per sweep over the columns
- *           (the paper's k_b, Section 2); 0 = auto.  Must be one of
- *           1, 2, 4, 8, 16 when given.
+ *           (the paper's k_b, Section 2); 0 = auto.  MULTIPASS: 1, 2, 4,
+ *           8 or 16; CHAIN: 4 or 8.
+ *   waves   CHAIN only: waves (bands) per workgroup, 1..16; 0 = auto
+ *           (sized so the workgroups match the CU count).
+ *   publish CHAIN only: columns between progress updates across
+ *           workgroups (rounded up to a power of 2); 0 = auto (32).
  */
 typedef struct rotseq_opts {
     int32_t arith;
     int32_t kernel;
     int32_t band;
-    int32_t reserved[5];
+    int32_t waves;
+    int32_t publish;
+    int32_t reserved[3];
 } rotseq_opts;
 
 /*
@@ -158,6 +168,14 @@ typedef struct rotseq_profile {
 } rotseq_profile;
 int rotseq_profile_enable(int on);
 int rotseq_profile_read(rotseq_profile *out, int reset);
+
+/*
+ * Sticky device-side error word of the current device.  Kernels OR
+ * ROTSEQ_E_* bits into it (ROTSEQ_E_TIMEOUT: a bounded wait between waves
+ * gave up, so the affected results are invalid).  This call synchronizes the
+ * device, returns the word and, if `reset` is nonzero, clears it.
+ */
+int rotseq_device_status(int reset);
 
 /* Static description of a return code. */
 const char *rotseq_strerror(int code);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librotseq.so")
 
 ARITH_AUTO, ARITH_EXACT, ARITH_FMA, ARITH_LIFT = 0, 1, 2, 3
-KERNEL_AUTO, KERNEL_MULTIPASS = 0, 1
+KERNEL_AUTO, KERNEL_MULTIPASS, KERNEL_CHAIN = 0, 1, 2
 
 _lib = None
 
@@ -26,7 +26,8 @@ class RotseqError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("arith", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("band", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("publish", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Profile(ctypes.Structure):
@@ -46,6 +47,11 @@ def profile_read(reset=False):
     if rc != 0:
         raise RotseqError(rc, "profile_read")
     return {f: getattr(out, f) for f, _ in Profile._fields_}
+
+
+def device_status(reset=False):
+    """Sticky device error bits (synchronizes the device); 0 means clean."""
+    return _load().rotseq_device_status(1 if reset else 0)
 
 
 def library_path():
@@ -76,6 +82,8 @@ def _load():
     lib.rotseq_strerror.argtypes = [i32]
     lib.rotseq_version.restype = i32
     lib.rotseq_version.argtypes = []
+    lib.rotseq_device_status.restype = i32
+    lib.rotseq_device_status.argtypes = [i32]
     lib.rotseq_profile_enable.restype = i32
     lib.rotseq_profile_enable.argtypes = [i32]
     lib.rotseq_profile_read.restype = i32

@@ -17,36 +17,168 @@ namespace rotseq {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool make_plan(Plan &p, int req_band)
+bool make_plan(Plan &p, int req_kernel, int req_band)
 {
+    p.kernel = req_kernel == 0 ? kChain : req_kernel;
     int band = req_band;
-    if (band == 0) {
-        band = 1;
-        while (band < 16 && band < p.k)
-            band *= 2;
-    }
-    if (band != 1 && band != 2 && band != 4 && band != 8 && band != 16)
+    if (p.kernel == kChain) {
+        if (band == 0)
+            band = 8;
+        if (band != 4 && band != 6 && band != 8)
+            return false;
+        p.unroll = chain_unroll(band);
+    } else if (p.kernel == kMultipass) {
+        if (band == 0) {
+            band = 1;
+            while (band < 16 && band < p.k)
+                band *= 2;
+        }
+        if (band != 1 && band != 2 && band != 4 && band != 8 && band != 16)
+            return false;
+        p.unroll = unroll_for_band(band);
+    } else {
         return false;
+    }
     p.band = band;
     p.npass = (int)((p.k + band - 1) / band);
-    p.unroll = unroll_for_band(band);
     const int64_t real_steps = p.n + band - 1;  // t = 0 .. n+K-2
     p.steps = (int)(((real_steps + p.unroll - 1) / p.unroll) * p.unroll);
     const int64_t n1 = p.n - 1;
+    const int64_t tiles = (p.m + 63) / 64;
     size_t off = 0;
     p.off_coef = off;
-    off = align256(off + (size_t)p.npass * p.steps * band * 2 * p.esize);
+    off = align256(off + (size_t)p.npass * (p.steps + 1) * band * 2 * p.esize);
     p.off_negmask = off;
     off = align256(off + (size_t)p.npass * n1 * sizeof(uint64_t));
     p.off_parity = off;
     off = align256(off + (size_t)(p.npass + 1) * n1);
     p.off_sign = off;
     off = align256(off + (size_t)p.n * p.esize);
+    p.off_flags = off;
+    off = align256(off + (size_t)tiles * p.npass * sizeof(int));
     p.total = off;
     return true;
 }
 
 namespace {
+
+struct DeviceInfo {
+    int cus = 0;
+    size_t max_lds = 0;
+    size_t lds_per_cu = 0;
+    int *status = nullptr;  // sticky device-side error word
+};
+
+int device_info(DeviceInfo &out)
+{
+    static std::mutex mu;
+    static std::map<int, DeviceInfo> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        DeviceInfo d;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return ROTSEQ_E_HIP;
+        d.cus = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return ROTSEQ_E_HIP;
+        d.max_lds = (size_t)v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess)
+            return ROTSEQ_E_HIP;
+        d.lds_per_cu = (size_t)v;
+        if (hipMalloc(&d.status, sizeof(int)) != hipSuccess)
+            return ROTSEQ_E_NOMEM;
+        if (hipMemset(d.status, 0, sizeof(int)) != hipSuccess)
+            return ROTSEQ_E_HIP;
+        if (hipDeviceSynchronize() != hipSuccess)
+            return ROTSEQ_E_HIP;
+        it = cache.emplace(dev, d).first;
+    }
+    out = it->second;
+    return ROTSEQ_SUCCESS;
+}
+
+}  // namespace
+
+hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
+{
+    if (p.kernel != kChain)
+        return hipSuccess;
+    DeviceInfo d;
+    if (device_info(d) != ROTSEQ_SUCCESS)
+        return hipErrorInvalidDevice;
+    const int64_t tiles = (p.m + 63) / 64;
+    const int64_t total = tiles * p.npass;
+    // Pick the workgroup size W (waves = bands per workgroup) and the number
+    // of workgroups resident per CU so that the ~total/W workgroups fill
+    // every CU evenly with as many waves as registers and LDS allow (up to
+    // kMaxWavesPerCU): waves hide each other's memory and scalar-load latency.
+    constexpr int kMaxWavesPerCU = 24;
+    int waves = 0, per_cu = 1;
+    size_t lds = 0;
+    if (req_waves > 0) {
+        waves = std::min(req_waves, 16);
+        lds = chain_lds_bytes(p.band, waves, p.esize);
+        while (waves > 1 && lds > d.max_lds)
+            lds = chain_lds_bytes(p.band, --waves, p.esize);
+    } else {
+        int best_waves_cu = -1;
+        for (int wpc = 1; wpc <= 4; ++wpc) {
+            const int64_t w = (total + (int64_t)wpc * d.cus - 1) / ((int64_t)wpc * d.cus);
+            if (w > 16 && wpc < 4)
+                continue;
+            const int wv = (int)std::max<int64_t>(1, std::min<int64_t>(16, w));
+            const size_t l = chain_lds_bytes(p.band, wv, p.esize);
+            if (l * wpc > d.lds_per_cu || l > d.max_lds)
+                continue;
+            int occ = 0;
+            if (chain_occupancy(p.band, p.arith, p.esize, wv, l, &occ) != hipSuccess || occ < wpc)
+                continue;
+            const int per = wv * wpc;
+            if (per > kMaxWavesPerCU && best_waves_cu >= 0)
+                continue;
+            if (per > best_waves_cu) {
+                best_waves_cu = per;
+                waves = wv;
+                per_cu = wpc;
+                lds = l;
+            }
+        }
+        if (waves == 0) {
+            waves = 1;
+            lds = chain_lds_bytes(p.band, 1, p.esize);
+        }
+    }
+    (void)per_cu;
+    p.waves = waves;
+    p.lds_bytes = lds;
+    p.nwg = (int)((total + waves - 1) / waves);
+    int occ = 0;
+    hipError_t e = chain_occupancy(p.band, p.arith, p.esize, waves, lds, &occ);
+    if (e != hipSuccess)
+        return e;
+    // Consecutive workgroups share tiles; placing them on one XCD keeps the
+    // hand-off in that XCD's L2.  Only safe when the whole grid is resident,
+    // since the remapped order no longer follows the dispatch order.
+    p.remap = (p.nwg % 8 == 0 && p.nwg >= 8 && (int64_t)p.nwg <= (int64_t)occ * d.cus) ? 1 : 0;
+    // Publish once per unrolled ring period (R columns) unless asked otherwise.
+    int publish = req_publish > 0 ? req_publish / p.unroll : 1;
+    int pow2 = 1;
+    while (pow2 < publish)
+        pow2 *= 2;
+    p.publish = pow2;
+    p.spin_limit = 1 << 22;
+    p.status = d.status;
+    return hipSuccess;
+}
+
+namespace {
+
 
 int check_args(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *C,
                int64_t ldc, const void *S, int64_t lds)
@@ -175,16 +307,19 @@ Profiler &profiler()
     return *p;
 }
 
-bool resolve(const rotseq_opts *opts, int &arith, int &band)
+bool resolve(const rotseq_opts *opts, int &arith, int &band, int &kernel)
 {
     arith = opts ? opts->arith : 0;
     band = opts ? opts->band : 0;
-    const int kernel = opts ? opts->kernel : 0;
+    kernel = opts ? opts->kernel : 0;
     if (arith == ROTSEQ_ARITH_AUTO)
         arith = kLift;
     if (arith != kExact && arith != kFma && arith != kLift)
         return false;
-    if (kernel != ROTSEQ_KERNEL_AUTO && kernel != ROTSEQ_KERNEL_MULTIPASS)
+    if (kernel != ROTSEQ_KERNEL_AUTO && kernel != ROTSEQ_KERNEL_MULTIPASS &&
+        kernel != ROTSEQ_KERNEL_CHAIN)
+        return false;
+    if (opts && (opts->waves < 0 || opts->waves > 16 || opts->publish < 0))
         return false;
     return true;
 }
@@ -192,8 +327,8 @@ bool resolve(const rotseq_opts *opts, int &arith, int &band)
 bool plan_for(Plan &p, int esize, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc,
               int64_t lds, const rotseq_opts *opts)
 {
-    int arith = 0, band = 0;
-    if (!resolve(opts, arith, band))
+    int arith = 0, band = 0, kernel = 0;
+    if (!resolve(opts, arith, band, kernel))
         return false;
     p = Plan{};
     p.m = m;
@@ -204,7 +339,7 @@ bool plan_for(Plan &p, int esize, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.lds = lds;
     p.arith = arith;
     p.esize = esize;
-    return make_plan(p, band);
+    return make_plan(p, kernel, band);
 }
 
 template <typename T>
@@ -221,6 +356,8 @@ int run(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C, int64_t 
         return ROTSEQ_E_UNSUPPORTED;
     if (n > INT32_MAX - 64 || p.steps <= 0)
         return ROTSEQ_E_UNSUPPORTED;
+    if (configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0) != hipSuccess)
+        return ROTSEQ_E_HIP;
     if (ws) {
         if (ws_bytes < p.total || ((uintptr_t)ws & 255) != 0)
             return ROTSEQ_E_WORKSPACE;
@@ -311,6 +448,24 @@ const char *rotseq_strerror(int code)
 }
 
 int rotseq_version(void) { return 100; }
+
+int rotseq_device_status(int reset)
+{
+    DeviceInfo d;
+    const int rc = device_info(d);
+    if (rc)
+        return rc;
+    if (hipDeviceSynchronize() != hipSuccess)
+        return ROTSEQ_E_HIP;
+    int v = 0;
+    if (hipMemcpy(&v, d.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (reset && hipMemset(d.status, 0, sizeof(int)) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (reset && hipDeviceSynchronize() != hipSuccess)
+        return ROTSEQ_E_HIP;
+    return v;
+}
 
 int rotseq_profile_enable(int on)
 {

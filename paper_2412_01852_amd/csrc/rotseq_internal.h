@@ -11,30 +11,48 @@ namespace rotseq {
 // Per-rotation arithmetic (values of rotseq_opts.arith after resolving AUTO).
 enum Arith : int { kExact = 1, kFma = 2, kLift = 3 };
 
+// Sweep kernel families (values of rotseq_opts.kernel after resolving AUTO).
+enum Kernel : int { kMultipass = 1, kChain = 2 };
+
 // Shape of one call after dispatch decisions: A is m x n (column-major, lda),
 // the k sequences are cut into `npass` bands of `band` sequences (the last
 // band is padded with identity rotations), and every sweep over the columns
 // takes `steps` wavefront steps (n + band - 1 rounded up to the kernel's
 // unroll length; steps past the last real one are identity).
+// The coefficient buffer holds steps + 1 records per band: the sweep may
+// prefetch the record after its last step, which is identity padding.
 struct Plan {
     int64_t m, n, k, lda, ldc, lds;
+    int kernel;  // Kernel
     int band;    // sequences per band (K)
     int npass;   // number of bands
     int steps;   // padded wavefront steps per band
     int unroll;  // kernel unroll length (register ring size)
     int arith;
     int esize;   // sizeof element: 8 (double) or 4 (float)
+    // Launch shape of the chain kernel (configure_launch).
+    int waves, nwg, remap, publish, spin_limit;
+    size_t lds_bytes;
+    int *status;  // sticky device error word (ROTSEQ_E_* bits)
     // Workspace layout (byte offsets from the workspace base, 256-aligned).
-    size_t off_coef, off_negmask, off_parity, off_sign, total;
+    size_t off_coef, off_negmask, off_parity, off_sign, off_flags, total;
 };
 
-// Fills the dispatch fields of `p` (band, npass, steps, unroll, offsets)
-// from its shape and the requested band (0 = auto).  Returns false when the
-// requested band is not supported.
-bool make_plan(Plan &p, int req_band);
+// Fills the shape-only fields of `p` (kernel, band, npass, steps, unroll,
+// workspace offsets) from its shape and the requested kernel and band
+// (0 = auto).  Returns false for unsupported requests.  Host-only.
+bool make_plan(Plan &p, int req_kernel, int req_band);
 
-// Register-ring length (= unroll length) of the sweep kernel for a band.
+// Fills the launch shape of `p` for the current device (queries its CU count
+// and occupancy).  `req_waves` > 0 forces the waves per workgroup.
+hipError_t configure_launch(Plan &p, int req_waves, int req_publish);
+
+// Register-ring length (= unroll length) of the sweep kernels for a band.
 int unroll_for_band(int band);
+int chain_unroll(int band);
+size_t chain_lds_bytes(int band, int waves, int esize);
+hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks);
+hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stream);
 
 // Launchers (rotseq_kernels.hip).  All are asynchronous on `stream` and
 // return the hipError_t of the launch.

@@ -37,6 +37,7 @@ def run_full(pb, dtype, opts=None):
     pad_before = padding_bits(A)
     rs.rotseq(A, C, S, opts=opts)
     torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
     got = rs.host_colmajor(A)
     ref = oracle.colmajor(widened(pb.A, dtype))
     oracle.rotseq(ref, oracle.colmajor(widened(pb.C, dtype)), oracle.colmajor(widened(pb.S, dtype)))
@@ -67,11 +68,13 @@ EDGE = [
 
 @pytest.mark.parametrize("m,n,k,pa,pc,ps", EDGE)
 @pytest.mark.parametrize("arith", ["exact", "lift"])
-def test_edges_fp64(m, n, k, pa, pc, ps, arith):
-    say(f"edge fp64 m={m} n={n} k={k} pads={pa},{pc},{ps} arith={arith}")
+@pytest.mark.parametrize("kernel", ["chain", "multipass"])
+def test_edges_fp64(m, n, k, pa, pc, ps, arith, kernel):
+    say(f"edge fp64 m={m} n={n} k={k} pads={pa},{pc},{ps} arith={arith} kernel={kernel}")
     pb = make_problem(m, n, k, seed=m + 7 * n + 13 * k,
                       lda=max(1, m) + pa, ldc=max(1, n - 1) + pc, lds=max(1, n - 1) + ps)
-    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith]})
+    kern = rs.KERNEL_CHAIN if kernel == "chain" else rs.KERNEL_MULTIPASS
+    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith], "kernel": kern})
     assert pad_ok, "padding rows of A were modified"
     if arith == "exact":
         assert np.array_equal(got, ref)
@@ -81,10 +84,37 @@ def test_edges_fp64(m, n, k, pa, pc, ps, arith):
 
 @pytest.mark.parametrize("band", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("arith", sorted(ARITHS))
-def test_bands_fp64(band, arith):
-    say(f"bands fp64 band={band} arith={arith}")
+def test_multipass_bands_fp64(band, arith):
+    say(f"multipass fp64 band={band} arith={arith}")
     pb = make_problem(200, 300, 37, seed=band)
-    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith], "band": band})
+    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith], "band": band,
+                                            "kernel": rs.KERNEL_MULTIPASS})
+    assert pad_ok
+    if arith == "exact":
+        assert np.array_equal(got, ref)
+    else:
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+
+
+CHAIN = [
+    # band, waves, publish: waves=1 puts every hand-off through A and the
+    # device-scope counters; publish=1 publishes after every column.
+    (4, 0, 0), (6, 0, 0), (8, 0, 0), (8, 1, 1), (4, 1, 32), (6, 2, 4), (8, 3, 2),
+    (4, 5, 8), (6, 16, 0), (8, 16, 1), (4, 7, 64),
+]
+
+
+@pytest.mark.parametrize("band,waves,publish", CHAIN)
+@pytest.mark.parametrize("arith", ["exact", "lift"])
+def test_chain_fp64(band, waves, publish, arith):
+    """Chains of band-waves: LDS hand-off inside a workgroup, A plus
+    device-scope progress counters across workgroups."""
+    say(f"chain fp64 band={band} waves={waves} publish={publish} arith={arith}")
+    pb = make_problem(333, 211, 59, seed=band * 100 + waves, lda=340)
+    got, ref, pad_ok = run_full(pb, "f64", {"arith": ARITHS[arith], "band": band,
+                                            "kernel": rs.KERNEL_CHAIN, "waves": waves,
+                                            "publish": publish})
+    assert pad_ok
     if arith == "exact":
         assert np.array_equal(got, ref)
     else:
@@ -116,6 +146,7 @@ def run_sampled(m, n, k, seed, dtype, opts=None):
     norms0 = torch.linalg.vector_norm(A.double(), dim=1)
     rs.rotseq(A, C, S, opts=opts)
     torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
     norms1 = torch.linalg.vector_norm(A.double(), dim=1)
     rows = sample_rows(m, np.random.Generator(np.random.PCG64(seed)))
     got = A[torch.as_tensor(rows, device=A.device)].double().cpu().numpy()
@@ -126,11 +157,13 @@ def run_sampled(m, n, k, seed, dtype, opts=None):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_target_10240_k192_sampled(dtype):
+@pytest.mark.parametrize("kernel", ["chain", "multipass"])
+def test_target_10240_k192_sampled(dtype, kernel):
     """m = n = 10240, k = 192: sampled rows against the oracle; every row's
     norm is preserved (an orthogonal transform)."""
-    say(f"target 10240x10240 k=192 {dtype} (sampled rows)")
-    err, drift = run_sampled(10240, 10240, 192, 2, dtype)
+    say(f"target 10240x10240 k=192 {dtype} kernel={kernel} (sampled rows)")
+    kern = rs.KERNEL_CHAIN if kernel == "chain" else rs.KERNEL_MULTIPASS
+    err, drift = run_sampled(10240, 10240, 192, 2, dtype, {"kernel": kern})
     say(f"  rel err {err:.3e}  max row-norm drift {drift:.3e}")
     assert err <= TOL[dtype]
     assert drift <= (1e-12 if dtype == "f64" else 1e-4)
