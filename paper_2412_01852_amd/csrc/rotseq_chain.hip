@@ -25,6 +25,8 @@
 // ROTSEQ_E_TIMEOUT in the status word and carries on with whatever data it
 // has, so the grid always drains.  All accesses stay in bounds whatever the
 // data (buffer descriptors for A, ring indices modulo RB for LDS).
+#include <type_traits>
+
 #include "rotseq.h"
 #include "rotseq_device.h"
 #include "rotseq_internal.h"
@@ -33,13 +35,21 @@ namespace rotseq {
 using namespace dev;
 namespace {
 
-// Column prefetch distance of the chain kernel: R = K + 1 + D steps form
-// one unrolled loop body and RB = R ring slots per LDS channel, so every
-// slot index in the body is a compile-time constant.
+// Geometry of the chain kernel.  A wave's register ring holds R = K + 1 + D
+// columns, D being how many steps ahead a column is fetched: far ahead from
+// A (HBM latency), one step ahead from an LDS channel.  Each LDS channel has
+// RB = 16 column slots.  The step loop is unrolled U = 16 steps, a multiple
+// of every R and of RB, so every ring, slot and coefficient index in the body
+// is a compile-time constant.
 template <int K>
 struct ChainGeom {
-    static constexpr int R = K <= 4 ? 8 : 16;
-    static constexpr int D = R - K - 1;
+    static constexpr int U = 16;
+    static constexpr int RB = 16;
+    static constexpr int R_lds = K <= 6 ? 8 : 16;     // ring of LDS-fed waves
+    static constexpr int R_glob = 16;                 // ring of A-fed waves
+    static constexpr int D_lds = R_lds - K - 1;
+    static constexpr int D_glob = R_glob - K - 1;
+    static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0, "geometry");
 };
 
 struct ChainArgs {
@@ -56,7 +66,7 @@ struct ChainArgs {
     int publish;     // columns (a power of 2) between cross-workgroup progress updates
     int spin_limit;  // polls before a wait gives up
     uint32_t lds_words;  // dynamic LDS size in 4-byte words
-    uint64_t coef;   // [nbands][steps + 1][K] coefficient pairs
+    uint64_t coef;   // [nbands][steps + 1 + 8][K] coefficient pairs
     uint64_t sign;   // [n] final column signs (lifting arithmetic)
     int *flags;      // [tiles][nbands] published progress (columns)
     int *status;     // error word
@@ -72,9 +82,13 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Keeps a running scalar counter opaque to the optimiser (see opaque()).
 __device__ __forceinline__ void opaque_i(int &x) { asm volatile("" : "+s"(x)); }
 
-__device__ __forceinline__ void record_timeout(int *status)
+// Which wait gave up, recorded in bits 8.. of the status word beside
+// ROTSEQ_E_TIMEOUT: LDS input, LDS output, device-scope flag.
+constexpr int kWaitLdsIn = 1 << 8, kWaitLdsOut = 1 << 9, kWaitFlag = 1 << 10;
+
+__device__ __forceinline__ void record_timeout(int *status, int kind)
 {
-    __hip_atomic_fetch_or(status, ROTSEQ_E_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(status, ROTSEQ_E_TIMEOUT | kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Waits until the LDS counter exceeds `need`; returns its value.  After a
@@ -82,12 +96,12 @@ __device__ __forceinline__ void record_timeout(int *status)
 // drains within one time-out per wave.
 typedef __attribute__((address_space(3))) volatile int lds_counter;
 
-__device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, int *status)
+__device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, int *status, int kind)
 {
     int v = uniform(*p);
     for (int polls = 0; v <= need; ++polls) {
         if (polls >= limit) {
-            record_timeout(status);
+            record_timeout(status, kind);
             limit = 0;
             return 0x7fffffff;
         }
@@ -104,7 +118,7 @@ __device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int *stat
     int v = uniform(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     for (int polls = 0; v <= need; ++polls) {
         if (polls >= (limit >> 4)) {
-            record_timeout(status);
+            record_timeout(status, kWaitFlag);
             limit = 0;
             return 0x7fffffff;
         }
@@ -114,33 +128,106 @@ __device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int *stat
     return v;
 }
 
-template <typename T, int K>
-__device__ __forceinline__ void load_coef(T (&ca)[K], T (&cb)[K], uint64_t wp)
+// ---------------------------------------------------------------- DPP
+//
+// Coefficients live in VGPRs: lane l holds the pair of rotation q = l mod 16
+// of the current step (the same in each 16-lane row), and an FMA reads it
+// broadcast across the row with the DPP row_newbcast:q source modifier.
+// This keeps them off the scalar path (whose loads complete out of order, so
+// they can only be prefetched one step ahead) and out of the SGPR file: one
+// vector load per step, issued kCoefAhead steps before use.
+
+template <int Q>
+__device__ __forceinline__ void fmac_bcast(double &x, double a, double y)
 {
-    ConstPairs<T> w = (ConstPairs<T>)wp;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        ca[q] = w[q].a;
-        cb[q] = w[q].b;
+    // x += a[lane Q of this row] * y
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(x) : "v"(a), "v"(y), "n"(Q));
+}
+template <int Q>
+__device__ __forceinline__ double bcast(double a)
+{
+    double r;
+    asm("v_mov_b64_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf" : "=v"(r) : "v"(a), "n"(Q));
+    return r;
+}
+// Rotation q of a step with its coefficient pair held in lane q of each row.
+// row_newbcast is a 64-bit DPP mode: FP64 lifting reads the coefficients
+// straight into its FMAs; the other FP64 modes broadcast them first; FP32
+// broadcasts its (a, b) pair as one 64-bit value.  A DPP source must not
+// have been written by a VALU instruction in the two preceding instructions
+// (the compiler cannot see the DPP inside the asm), so every DPP source here
+// is a register written by the coefficient load itself; tests scan the ISA.
+template <int ARITH, int Q>
+__device__ __forceinline__ void rotate_bcast(double &x, double &y, double a, double b)
+{
+    if constexpr (ARITH == kLift) {
+        fmac_bcast<Q>(x, a, y);
+        fmac_bcast<Q>(y, b, x);
+        fmac_bcast<Q>(x, a, y);
+    } else {
+        rotate<ARITH>(x, y, bcast<Q>(a), bcast<Q>(b));
     }
 }
+// FP32: `pair` holds the loaded (a, b) bits of lane q.
+template <int ARITH, int Q>
+__device__ __forceinline__ void rotate_bcast_pair(float &x, float &y, double pair)
+{
+    const unsigned long long p = __builtin_bit_cast(unsigned long long, bcast<Q>(pair));
+    rotate<ARITH>(x, y, __builtin_bit_cast(float, (unsigned)p), __builtin_bit_cast(float, (unsigned)(p >> 32)));
+}
+
+template <int Q, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (Q < N) {
+        f(std::integral_constant<int, Q>{});
+        static_for<Q + 1, N>(f);
+    }
+}
+
+// One coefficient record lane: the pair (a, b) as raw bits.
+template <typename T>
+struct CoefLane;
+template <>
+struct CoefLane<double> {
+    typedef unsigned int bits __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ bits load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    }
+    static __device__ __forceinline__ double a(bits v)
+    {
+        return __builtin_bit_cast(double, (unsigned long long)v.x | ((unsigned long long)v.y << 32));
+    }
+    static __device__ __forceinline__ double b(bits v)
+    {
+        return __builtin_bit_cast(double, (unsigned long long)v.z | ((unsigned long long)v.w << 32));
+    }
+};
+template <>
+struct CoefLane<float> {
+    typedef unsigned int bits __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ bits load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    }
+    static __device__ __forceinline__ double pair(bits v) { return __builtin_bit_cast(double, v); }
+};
 
 // Where a band-wave's columns come from and go to.
 enum In : int { kInLds = 0, kInFresh = 1, kInWait = 2 };       // LDS channel / A (band 0) / A after a flag
 enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel / A + flag / A (last band)
 
-// One band-wave.  The step loop is unrolled over one ring period of R steps
-// so every register-ring slot, LDS slot and coefficient offset is a
-// compile-time constant.
+// One band-wave, unrolled over U steps.
 //
-// Flow control is per column.  A consumer (LDS input) may read column c
-// once produced > c; a producer (LDS output) may overwrite the slot of
-// column c - RB once consumed > c - RB.  Both counters are re-read
-// asynchronously every kPollEvery steps (an LDS load whose value is folded
-// in the next time), so a wave only stalls when its neighbour really is
-// behind; when it must wait it waits for extra headroom (kInSlack columns,
-// kOutSlack slots) so the next wait is far away.  kInSlack + kOutSlack <=
-// RB - 1 keeps the two sides from ever waiting on each other.
+// Flow control is per column, evaluated once per group of G = 4 steps.  A
+// consumer (LDS input) may read column c once produced > c; a producer (LDS
+// output) may overwrite the slot of column c - RB once consumed > c - RB.
+// Both counters are published once per group and re-read asynchronously
+// (an LDS load issued one group earlier), so a wave only stalls when its
+// neighbour really is behind; when it must wait it waits for extra headroom
+// (kInSlack columns, kOutSlack slots) so the next wait is further away.
 //
 // Channel reads and writes are unconditional: columns outside [0, n)
 // travel as data too (zeros, or past n possibly an older finite column of
@@ -149,14 +236,22 @@ enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel 
 template <typename T, int K, int ARITH, int IN, int OUT>
 __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, int w, char *lds_generic)
 {
-    constexpr int D = ChainGeom<K>::D;
-    constexpr int R = ChainGeom<K>::R;
-    constexpr int RB = R;
+    using Geo = ChainGeom<K>;
+    constexpr int U = Geo::U;
+    constexpr int RB = Geo::RB;
+    constexpr int R = IN == kInLds ? Geo::R_lds : Geo::R_glob;
+    constexpr int D = R - K - 1;
     constexpr int SLOT = kWave;  // elements per ring slot
-    constexpr int kPollEvery = 4;
-    constexpr int kInSlack = RB / 2;
-    constexpr int kOutSlack = RB - 1 - kInSlack;
-    static_assert(R % kPollEvery == 0, "poll cadence must divide the unroll");
+    constexpr int G = 4;         // steps per flow-control group
+    // Counters move in steps of G, so a blocked consumer (waiting for
+    // produced >= lc + G + kInSlack) and a blocked producer (waiting for
+    // consumed >= sc + G - RB + kOutSlack) can never block each other as
+    // long as kInSlack + kOutSlack <= RB + 1 - 2G.
+    constexpr int kSlack = RB + 1 - 2 * G;
+    constexpr int kInSlack = (kSlack + 1) / 2;
+    constexpr int kOutSlack = kSlack - kInSlack;
+    static_assert(U % G == 0, "groups must tile the unroll");
+    static_assert(kInSlack >= 0 && kOutSlack >= 0, "ring too small for the group size");
     typedef __attribute__((address_space(3))) T lds_T;
     const int n = a.n;
     const int lane = threadIdx.x & (kWave - 1);
@@ -181,7 +276,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     const int pubmask = a.publish - 1;
 
     // Input columns < in_known exist; the LDS consumer has read columns
-    // < out_known.  in_poll / out_poll: counter values read asynchronously.
+    // < out_known.  in_poll / out_poll: counter values read a group ago.
     int in_known = IN == kInFresh ? 0x7fffffff : 0;
     int out_known = 0;
     int in_poll = 0, out_poll = 0;
@@ -194,43 +289,65 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     // Fetch stream: next input column lc (at address lp in A).
     int lc = 0;
     uint64_t lp = tileaddr;
-    auto fetch = [&](T &dst, int slot) {
+    auto ensure_in = [&](int cols) {  // the next `cols` fetches must exist
         if constexpr (IN != kInFresh) {
-            if (lc >= in_known) {
-                const int need = (lc + kInSlack < n ? lc + kInSlack : n) - 1;
-                if (lc < n) {
-                    if constexpr (IN == kInLds)
-                        in_known = wait_lds(prod_in, need, limit, status);
-                    else
-                        in_known = wait_flag(flag_in, need, limit, status);
-                }
+            if (lc + cols > in_known && lc < n) {
+                const int want = lc + cols + kInSlack;
+                const int need = (want < n ? want : n) - 1;
+                if constexpr (IN == kInLds)
+                    in_known = wait_lds(prod_in, need, limit, status, kWaitLdsIn);
+                else
+                    in_known = wait_flag(flag_in, need, limit, status);
             }
         }
+    };
+    auto fetch = [&](T &dst, int slot) {
         if constexpr (IN == kInLds) {
             dst = ring_in[slot * SLOT];
-            compiler_fence();
-            *cons_in = lc + 1;
         } else {
             dst = buf_load<kPolicyDevice>(T(), make_rsrc(lp, lc < n ? rowbytes : 0u), voff);
             lp += ldab;
             opaque(lp);
         }
         ++lc;
-        opaque_i(lc);
     };
 
+    ensure_in(D + 1);
 #pragma unroll
     for (int c = 0; c <= D; ++c)
         fetch(ring[c], c % RB);
+    opaque_i(lc);
+    if constexpr (IN == kInLds) {
+        compiler_fence();
+        *cons_in = lc;
+        in_poll = *prod_in;
+    } else if constexpr (IN == kInWait) {
+        in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if constexpr (OUT == kOutLds)
+        out_poll = *cons_out;
 
     // Output stream: next output column sc (at address sp in A).
     int sc = -(K - 1);
     uint64_t sp = tileaddr - (uint64_t)(K - 1) * ldab;
 
-    constexpr uint64_t kStepBytes = K * sizeof(CoefPair<T>);
-    uint64_t wblk = a.coef + (uint64_t)b * (a.steps + 1) * kStepBytes;
-    T ca[K], cb[K];
-    load_coef<T, K>(ca, cb, wblk);
+    // Coefficient pipeline: record of step t is loaded into cf[t % kCoefAhead]
+    // kCoefAhead steps before step t.  Lane l loads pair min(l mod 16, K-1);
+    // only lanes l mod 16 < K are ever read.
+    constexpr int kCoefAhead = 8;
+    static_assert(U % kCoefAhead == 0, "coefficient ring must tile the unroll");
+    using CL = CoefLane<T>;
+    constexpr int kStepBytes = K * (int)sizeof(CoefPair<T>);
+    const int q16 = lane & 15;
+    const int cvoff = (q16 < K ? q16 : K - 1) * (int)sizeof(CoefPair<T>);
+    const uint64_t cbase = a.coef + (uint64_t)b * (a.steps + 1 + kCoefAhead) * kStepBytes;
+    const __amdgpu_buffer_rsrc_t crs =
+        make_rsrc(cbase, (uint32_t)((a.steps + 1 + kCoefAhead) * kStepBytes));
+    int coff = 0;  // byte offset of the record of step t0 (block base)
+    typename CL::bits cf[kCoefAhead];
+#pragma unroll
+    for (int i = 0; i < kCoefAhead; ++i)
+        cf[i] = CL::load(crs, cvoff, i * kStepBytes);
     ConstScalars<T> sign = (ConstScalars<T>)a.sign;
     constexpr bool kSign = OUT == kOutFinal && ARITH == kLift;
     T sg = T(1);
@@ -238,48 +355,56 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         sg = sign[0];
     int blk = 0;
 
-    for (int t0 = 0; t0 < a.steps; t0 += R) {
+    for (int t0 = 0; t0 < a.steps; t0 += U) {
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-            // Fold in the counters read kPollEvery steps ago and read them again.
-            if (u % kPollEvery == 0) {
+        for (int u = 0; u < U; ++u) {
+            if (u % G == 0) {
+                // Group prologue: fold in the counters read a group ago, make
+                // sure this group's G fetches and G slot writes are allowed,
+                // and re-read the counters for the next group.
                 if constexpr (IN == kInLds || IN == kInWait) {
                     const int v = uniform(in_poll);
                     in_known = v > in_known ? v : in_known;
-                    if constexpr (IN == kInLds)
-                        in_poll = *prod_in;
-                    else
-                        in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                ensure_in(G);
                 if constexpr (OUT == kOutLds) {
                     const int v = uniform(out_poll);
                     out_known = v > out_known ? v : out_known;
-                    out_poll = *cons_out;
+                    if (sc + G > out_known + RB)  // slot of column sc+G-1-RB must be read
+                        out_known = wait_lds(cons_out, sc + G - 1 - RB + kOutSlack, limit, status, kWaitLdsOut);
                 }
+                if constexpr (IN == kInLds)
+                    in_poll = *prod_in;
+                else if constexpr (IN == kInWait)
+                    in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if constexpr (OUT == kOutLds)
+                    out_poll = *cons_out;
             }
-            // Next step's coefficients (the record after the last step is padding).
-            T na[K], nb[K];
-            load_coef<T, K>(na, nb, wblk + (uint64_t)(u + 1) * kStepBytes);
+            // This step's coefficients; refill the slot kCoefAhead steps ahead
+            // (records past the last step are identity padding).
+            const typename CL::bits cur = cf[u % kCoefAhead];
+            cf[u % kCoefAhead] = CL::load(crs, cvoff, coff + (u + kCoefAhead) * kStepBytes);
             // Column t+1+D replaces column t-K, finished last step.
             fetch(ring[(u + D + 1) % R], (u + D + 1) % RB);
-#pragma unroll
-            for (int q = 0; q < K; ++q)
-                rotate<ARITH>(ring[(u - q + R) % R], ring[(u - q + 1 + R) % R], ca[q], cb[q]);
+            static_for<0, K>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if constexpr (sizeof(T) == 8)
+                    rotate_bcast<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
+                                           CL::a(cur), CL::b(cur));
+                else
+                    rotate_bcast_pair<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
+                                                CL::pair(cur));
+            });
             // Column sc = t-K+1 has seen the whole band.
-            T val = ring[(u - K + 1 + R) % R];
+            T val = ring[(u - K + 1 + U) % R];
             if constexpr (OUT == kOutLds) {
-                if (sc >= out_known + RB) {
-                    // Slot of column sc - RB must have been read.
-                    out_known = wait_lds(cons_out, sc - RB + kOutSlack, limit, status);
-                }
-                ring_out[((u - K + 1 + RB) % RB) * SLOT] = val;
-                compiler_fence();
-                *prod_out = sc + 1;
+                ring_out[((u - K + 1 + U) % RB) * SLOT] = val;
             } else {
-                const bool valid = (unsigned)sc < (unsigned)n;
+                const int c = sc + (u % G);
+                const bool valid = (unsigned)c < (unsigned)n;
                 if constexpr (kSign) {
                     val *= sg;
-                    const int cn = sc + 1;
+                    const int cn = c + 1;
                     sg = sign[(unsigned)cn < (unsigned)n ? cn : 0];
                 }
                 if constexpr (OUT == kOutPublish)
@@ -289,29 +414,31 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                 sp += ldab;
                 opaque(sp);
             }
-            ++sc;
-            opaque_i(sc);
-            if constexpr (OUT == kOutPublish) {
-                // Columns < sc - kPublishLag are complete once at most
-                // kPublishLag vector memory operations are outstanding.
-                if (u == R - 1) {
-                    ++blk;
-                    if ((blk & pubmask) == 0 && sc > kPublishLag && sc - kPublishLag < n) {
-                        wait_vmem_at_most<kPublishLag>();
-                        __hip_atomic_store(flag_out, sc - kPublishLag, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                ca[q] = na[q];
-                cb[q] = nb[q];
+            if (u % G == G - 1) {
+                // Group epilogue: publish progress.
+                sc += G;
+                opaque_i(lc);
+                opaque_i(sc);
+                compiler_fence();
+                if constexpr (IN == kInLds)
+                    *cons_in = lc;
+                if constexpr (OUT == kOutLds)
+                    *prod_out = sc;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        wblk += R * kStepBytes;
-        opaque(wblk);
+        coff += U * kStepBytes;
+        opaque_i(coff);
+        if constexpr (OUT == kOutPublish) {
+            // Columns < sc - kPublishLag are complete once at most
+            // kPublishLag vector memory operations are outstanding.
+            ++blk;
+            if ((blk & pubmask) == 0 && sc > kPublishLag && sc - kPublishLag < n) {
+                wait_vmem_at_most<kPublishLag>();
+                __hip_atomic_store(flag_out, sc - kPublishLag, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
     if constexpr (OUT == kOutPublish) {
         wait_vmem_at_most<0>();
@@ -431,13 +558,14 @@ const void *chain_kernel_fn(int band, int arith)
 
 int chain_unroll(int band)
 {
-    return band == 4 ? ChainGeom<4>::R : band == 6 ? ChainGeom<6>::R : ChainGeom<8>::R;
+    (void)band;
+    return ChainGeom<8>::U;
 }
 
 size_t chain_lds_bytes(int band, int waves, int esize)
 {
-    const int R = chain_unroll(band);
-    return kCounters * sizeof(int) + (size_t)(waves > 1 ? waves - 1 : 0) * R * kWave * esize;
+    (void)band;
+    return kCounters * sizeof(int) + (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
 }
 
 hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks)

@@ -40,6 +40,7 @@ bool make_plan(Plan &p, int req_kernel, int req_band)
         return false;
     }
     p.band = band;
+    p.pad = p.kernel == kChain ? 9 : 1;
     p.npass = (int)((p.k + band - 1) / band);
     const int64_t real_steps = p.n + band - 1;  // t = 0 .. n+K-2
     p.steps = (int)(((real_steps + p.unroll - 1) / p.unroll) * p.unroll);
@@ -47,7 +48,7 @@ bool make_plan(Plan &p, int req_kernel, int req_band)
     const int64_t tiles = (p.m + 63) / 64;
     size_t off = 0;
     p.off_coef = off;
-    off = align256(off + (size_t)p.npass * (p.steps + 1) * band * 2 * p.esize);
+    off = align256(off + (size_t)p.npass * (p.steps + p.pad) * band * 2 * p.esize);
     p.off_negmask = off;
     off = align256(off + (size_t)p.npass * n1 * sizeof(uint64_t));
     p.off_parity = off;
@@ -114,11 +115,12 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
         return hipErrorInvalidDevice;
     const int64_t tiles = (p.m + 63) / 64;
     const int64_t total = tiles * p.npass;
-    // Pick the workgroup size W (waves = bands per workgroup) and the number
-    // of workgroups resident per CU so that the ~total/W workgroups fill
-    // every CU evenly with as many waves as registers and LDS allow (up to
-    // kMaxWavesPerCU): waves hide each other's memory and scalar-load latency.
-    constexpr int kMaxWavesPerCU = 24;
+    // Pick W (waves = bands per workgroup).  Each candidate is costed as
+    // rounds x (waves per SIMD in a round): `occ` workgroups fit on a CU at
+    // once (registers and LDS), so ceil(nwg / (occ * CUs)) rounds run one
+    // after another, and within a round the busiest SIMD holds
+    // ceil(W * wgs_per_cu / 4) waves.  Ties go to fewer workgroups (fewer
+    // hand-offs through A).
     int waves = 0, per_cu = 1;
     size_t lds = 0;
     if (req_waves > 0) {
@@ -127,25 +129,25 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
         while (waves > 1 && lds > d.max_lds)
             lds = chain_lds_bytes(p.band, --waves, p.esize);
     } else {
-        int best_waves_cu = -1;
-        for (int wpc = 1; wpc <= 4; ++wpc) {
-            const int64_t w = (total + (int64_t)wpc * d.cus - 1) / ((int64_t)wpc * d.cus);
-            if (w > 16 && wpc < 4)
-                continue;
-            const int wv = (int)std::max<int64_t>(1, std::min<int64_t>(16, w));
+        double best = 1e300;
+        for (int wv = 1; wv <= 16; ++wv) {
             const size_t l = chain_lds_bytes(p.band, wv, p.esize);
-            if (l * wpc > d.lds_per_cu || l > d.max_lds)
-                continue;
+            if (l > d.max_lds)
+                break;
             int occ = 0;
-            if (chain_occupancy(p.band, p.arith, p.esize, wv, l, &occ) != hipSuccess || occ < wpc)
+            if (chain_occupancy(p.band, p.arith, p.esize, wv, l, &occ) != hipSuccess || occ < 1)
                 continue;
-            const int per = wv * wpc;
-            if (per > kMaxWavesPerCU && best_waves_cu >= 0)
-                continue;
-            if (per > best_waves_cu) {
-                best_waves_cu = per;
+            const int64_t nwg = (total + wv - 1) / wv;
+            const int64_t slots = (int64_t)occ * d.cus;
+            const int64_t rounds = (nwg + slots - 1) / slots;
+            const int64_t in_round = std::min<int64_t>(nwg, slots);
+            const int64_t wg_per_cu = (in_round + d.cus - 1) / d.cus;
+            const int64_t simd_waves = (wv * wg_per_cu + 3) / 4;
+            const double cost = (double)rounds * (double)simd_waves + 1e-6 * (double)nwg;
+            if (cost < best) {
+                best = cost;
                 waves = wv;
-                per_cu = wpc;
+                per_cu = (int)wg_per_cu;
                 lds = l;
             }
         }

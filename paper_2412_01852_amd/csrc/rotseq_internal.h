@@ -19,14 +19,16 @@ enum Kernel : int { kMultipass = 1, kChain = 2 };
 // band is padded with identity rotations), and every sweep over the columns
 // takes `steps` wavefront steps (n + band - 1 rounded up to the kernel's
 // unroll length; steps past the last real one are identity).
-// The coefficient buffer holds steps + 1 records per band: the sweep may
-// prefetch the record after its last step, which is identity padding.
+// The coefficient buffer holds steps + pad records per band (pad = 1 for the
+// multipass kernel, 9 for the chain kernel): sweeps prefetch records past
+// their last step, which are identity padding.
 struct Plan {
     int64_t m, n, k, lda, ldc, lds;
     int kernel;  // Kernel
     int band;    // sequences per band (K)
     int npass;   // number of bands
     int steps;   // padded wavefront steps per band
+    int pad;     // identity records after the last step of each band
     int unroll;  // kernel unroll length (register ring size)
     int arith;
     int esize;   // sizeof element: 8 (double) or 4 (float)

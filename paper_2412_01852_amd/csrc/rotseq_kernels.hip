@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kWave) void sweep_multipass(T *__restrict__ A, int6
     const uint64_t tile = (uint64_t)(A + i0);
     const uint64_t ldab = (uint64_t)lda * sizeof(T);
     for (int pass = 0; pass < npass; ++pass) {
-        ConstPairs<T> w = (ConstPairs<T>)(coef + (int64_t)pass * (steps + 1) * K);
+        ConstPairs<T> w = (ConstPairs<T>)(coef + (int64_t)pass * (steps + 1) * K);  // pad = 1
         if (ARITH == kLift && pass == npass - 1)
             sweep_band<T, K, ARITH, true>(tile, ldab, rowbytes, voff, (int)n, w, steps,
                                           (ConstScalars<T>)sign);
@@ -254,22 +254,22 @@ __global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__res
     sign[c] = f ? T(-1) : T(1);
 }
 
-// coef[(pass*(steps+1) + t)*K + q] = coefficients of rotation (t-q, pass*K+q),
-// or the identity where that rotation does not exist (t = steps is always
+// coef[(pass*(steps+pad) + t)*K + q] = coefficients of rotation (t-q, pass*K+q),
+// or the identity where that rotation does not exist (t >= steps is always
 // identity padding).
 template <typename T>
 __global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S,
-                          int64_t lds, int64_t n1, int64_t k, int K, int steps, int npass,
+                          int64_t lds, int64_t n1, int64_t k, int K, int steps, int pad, int npass,
                           int arith, const uint64_t *__restrict__ negmask,
                           const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)npass * (steps + 1) * K;
+    const int64_t total = (int64_t)npass * (steps + pad) * K;
     if (idx >= total)
         return;
     const int q = (int)(idx % K);
-    const int64_t t = (idx / K) % (steps + 1);
-    const int64_t pass = idx / ((int64_t)K * (steps + 1));
+    const int64_t t = (idx / K) % (steps + pad);
+    const int64_t pass = idx / ((int64_t)K * (steps + pad));
     const int64_t j = t - q, p = pass * K + q;
     CoefPair<T> out;
     if (j >= 0 && j < n1 && p < k) {
@@ -329,13 +329,13 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
         prep_parity<<<blocks_for(n1, B), B, 0, st>>>(negmask, n1, p.npass, parity);
         prep_sign<T><<<blocks_for(p.n, B), B, 0, st>>>(parity + (int64_t)p.npass * n1, p.n, sign);
     }
-    const int64_t total = (int64_t)p.npass * (p.steps + 1) * p.band;
+    const int64_t total = (int64_t)p.npass * (p.steps + p.pad) * p.band;
     if (p.kernel == kChain) {
         const int64_t words = ((p.m + 63) / 64) * (int64_t)p.npass;
         prep_zero<<<blocks_for(words, B), B, 0, st>>>((int *)(ws + p.off_flags), words);
     }
     prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.ldc, S, p.lds, n1, p.k, p.band, p.steps,
-                                                    p.npass, p.arith, negmask, parity, coef);
+                                                    p.pad, p.npass, p.arith, negmask, parity, coef);
     return hipGetLastError();
 }
 
