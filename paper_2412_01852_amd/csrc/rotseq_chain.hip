@@ -177,6 +177,46 @@ __device__ __forceinline__ void rotate_bcast_pair(float &x, float &y, double pai
     rotate<ARITH>(x, y, __builtin_bit_cast(float, (unsigned)p), __builtin_bit_cast(float, (unsigned)(p >> 32)));
 }
 
+// All K lifting rotations of one step, FP64, in one asm block: rotation q
+// acts on (x, y) = (column t-q, column t-q+1) = (c[q+1], c[q]), with its
+// coefficients in lane q of each row of `a` and `b`.  One block per step
+// keeps the compiler from padding every FMA pair with wait states (it must
+// assume any asm operand may be a DPP source); inside the block the only
+// DPP sources are `a` and `b`, written by the coefficient load, and plain
+// VALU dependencies are interlocked by the hardware.
+#define ROTSEQ_FMAC(X, A, Y, Q) "v_fmac_f64_dpp %" #X ", %" #A ", %" #Y " row_newbcast:" #Q " row_mask:0xf bank_mask:0xf\n"
+#define ROTSEQ_ROT(Q, X, Y) ROTSEQ_FMAC(X, 9, Y, Q) ROTSEQ_FMAC(Y, 10, X, Q) ROTSEQ_FMAC(X, 9, Y, Q)
+template <int K>
+__device__ __forceinline__ void lift_step(double (&c)[9], double a, double b);
+template <>
+__device__ __forceinline__ void lift_step<8>(double (&c)[9], double a, double b)
+{
+    asm(ROTSEQ_ROT(0, 1, 0) ROTSEQ_ROT(1, 2, 1) ROTSEQ_ROT(2, 3, 2) ROTSEQ_ROT(3, 4, 3)
+        ROTSEQ_ROT(4, 5, 4) ROTSEQ_ROT(5, 6, 5) ROTSEQ_ROT(6, 7, 6) ROTSEQ_ROT(7, 8, 7)
+        : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
+          "+v"(c[7]), "+v"(c[8])
+        : "v"(a), "v"(b));
+}
+template <>
+__device__ __forceinline__ void lift_step<6>(double (&c)[9], double a, double b)
+{
+    asm(ROTSEQ_ROT(0, 1, 0) ROTSEQ_ROT(1, 2, 1) ROTSEQ_ROT(2, 3, 2) ROTSEQ_ROT(3, 4, 3)
+        ROTSEQ_ROT(4, 5, 4) ROTSEQ_ROT(5, 6, 5)
+        : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
+          "+v"(c[7]), "+v"(c[8])
+        : "v"(a), "v"(b));
+}
+template <>
+__device__ __forceinline__ void lift_step<4>(double (&c)[9], double a, double b)
+{
+    asm(ROTSEQ_ROT(0, 1, 0) ROTSEQ_ROT(1, 2, 1) ROTSEQ_ROT(2, 3, 2) ROTSEQ_ROT(3, 4, 3)
+        : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
+          "+v"(c[7]), "+v"(c[8])
+        : "v"(a), "v"(b));
+}
+#undef ROTSEQ_ROT
+#undef ROTSEQ_FMAC
+
 template <int Q, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f)
 {
@@ -386,15 +426,27 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
             cf[u % kCoefAhead] = CL::load(crs, cvoff, coff + (u + kCoefAhead) * kStepBytes);
             // Column t+1+D replaces column t-K, finished last step.
             fetch(ring[(u + D + 1) % R], (u + D + 1) % RB);
-            static_for<0, K>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                if constexpr (sizeof(T) == 8)
-                    rotate_bcast<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
-                                           CL::a(cur), CL::b(cur));
-                else
-                    rotate_bcast_pair<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
-                                                CL::pair(cur));
-            });
+            if constexpr (sizeof(T) == 8 && ARITH == kLift) {
+                // c[j] = column t+1-j, j = 0..K (unused operands are dummies).
+                double c[9];
+#pragma unroll
+                for (int j = 0; j < 9; ++j)
+                    c[j] = j <= K ? ring[(u + 1 - j + U) % R] : 0.0;
+                lift_step<K>(c, CL::a(cur), CL::b(cur));
+#pragma unroll
+                for (int j = 0; j <= K; ++j)
+                    ring[(u + 1 - j + U) % R] = c[j];
+            } else {
+                static_for<0, K>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    if constexpr (sizeof(T) == 8)
+                        rotate_bcast<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
+                                               CL::a(cur), CL::b(cur));
+                    else
+                        rotate_bcast_pair<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
+                                                    CL::pair(cur));
+                });
+            }
             // Column sc = t-K+1 has seen the whole band.
             T val = ring[(u - K + 1 + U) % R];
             if constexpr (OUT == kOutLds) {
