@@ -3,8 +3,10 @@
     python -m paper_2412_01852_amd.build
 
 Every source is compiled with hipcc for --offload-arch=gfx950 only, with
-packed FP32 instructions disabled (-target-feature -packed-fp32-ops), then
-linked into paper_2412_01852_amd/librotseq.so next to this file.
+packed FP32 instructions disabled (-target-feature -packed-fp32-ops) and the
+atomic optimizer off (it would turn the chain kernel's single-lane LDS counter
+increments into wave-wide reductions), then linked into
+paper_2412_01852_amd/librotseq.so next to this file.
 """
 import concurrent.futures as cf
 import os
@@ -24,6 +26,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

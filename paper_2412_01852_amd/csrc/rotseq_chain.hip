@@ -93,15 +93,18 @@ __device__ __forceinline__ void record_timeout(int *status, int kind)
 
 // Waits until the LDS counter exceeds `need`; returns its value.  After a
 // timeout `limit` drops to 0, so the wave never waits again and the grid
-// drains within one time-out per wave.
+// drains within one time-out per wave; the kind of wait that gave up is
+// collected in `timed_out` and written to the status word once, when the
+// wave ends (a memory write inside the step loop would make the compiler
+// drain every outstanding vector memory operation at each wait site).
 typedef __attribute__((address_space(3))) volatile int lds_counter;
 
-__device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, int *status, int kind)
+__device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, int &timed_out, int kind)
 {
     int v = uniform(*p);
     for (int polls = 0; v <= need; ++polls) {
         if (polls >= limit) {
-            record_timeout(status, kind);
+            timed_out |= kind;
             limit = 0;
             return 0x7fffffff;
         }
@@ -111,14 +114,34 @@ __device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, in
     return v;
 }
 
+// Adds 1 to an LDS counter from the wave's first lane only (`leader`):
+// one ds_add_u32 under a single-lane exec mask, no VALU work in the loop
+// (the library is built with the atomic optimizer off, which would otherwise
+// rewrite this into a wave-wide reduction).
+__device__ __forceinline__ void lds_inc(lds_counter *p, bool leader)
+{
+    if (leader)
+        __hip_atomic_fetch_add((__attribute__((address_space(3))) int *)p, 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The same LDS address, pinned in a VGPR once, so that lds_inc in the step
+// loop needs no VALU move to form its address operand.
+__device__ __forceinline__ lds_counter *addr_in_vgpr(lds_counter *p)
+{
+    uint32_t v = (uint32_t)(uintptr_t)p;
+    asm volatile("" : "+v"(v));
+    return (lds_counter *)(uintptr_t)v;
+}
+
 // Waits until the device-scope progress counter exceeds `need` (polls cost
 // a memory round trip, so they get a sixteenth of the LDS budget).
-__device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int *status)
+__device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int &timed_out)
 {
     int v = uniform(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     for (int polls = 0; v <= need; ++polls) {
         if (polls >= (limit >> 4)) {
-            record_timeout(status, kWaitFlag);
+            timed_out |= kWaitFlag;
             limit = 0;
             return 0x7fffffff;
         }
@@ -130,12 +153,12 @@ __device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int *stat
 
 // ---------------------------------------------------------------- DPP
 //
-// Coefficients live in VGPRs: lane l holds the pair of rotation q = l mod 16
-// of the current step (the same in each 16-lane row), and an FMA reads it
-// broadcast across the row with the DPP row_newbcast:q source modifier.
+// Coefficients live in VGPRs: one vector load brings the records of
+// 16/K consecutive steps, lane l of every 16-lane row holding pair l mod 16
+// of them (rotation q of the j-th step in lane j*K + q), and an FMA reads a
+// pair broadcast across the row with the DPP row_newbcast source modifier.
 // This keeps them off the scalar path (whose loads complete out of order, so
-// they can only be prefetched one step ahead) and out of the SGPR file: one
-// vector load per step, issued kCoefAhead steps before use.
+// they can only be prefetched one step ahead) and out of the SGPR file.
 
 template <int Q>
 __device__ __forceinline__ void fmac_bcast(double &x, double a, double y)
@@ -179,41 +202,37 @@ __device__ __forceinline__ void rotate_bcast_pair(float &x, float &y, double pai
 
 // All K lifting rotations of one step, FP64, in one asm block: rotation q
 // acts on (x, y) = (column t-q, column t-q+1) = (c[q+1], c[q]), with its
-// coefficients in lane q of each row of `a` and `b`.  One block per step
+// coefficients in lane OFF+q of each row of `a` and `b`.  One block per step
 // keeps the compiler from padding every FMA pair with wait states (it must
 // assume any asm operand may be a DPP source); inside the block the only
 // DPP sources are `a` and `b`, written by the coefficient load, and plain
-// VALU dependencies are interlocked by the hardware.
-#define ROTSEQ_FMAC(X, A, Y, Q) "v_fmac_f64_dpp %" #X ", %" #A ", %" #Y " row_newbcast:" #Q " row_mask:0xf bank_mask:0xf\n"
-#define ROTSEQ_ROT(Q, X, Y) ROTSEQ_FMAC(X, 9, Y, Q) ROTSEQ_FMAC(Y, 10, X, Q) ROTSEQ_FMAC(X, 9, Y, Q)
-template <int K>
-__device__ __forceinline__ void lift_step(double (&c)[9], double a, double b);
-template <>
-__device__ __forceinline__ void lift_step<8>(double (&c)[9], double a, double b)
+// VALU dependencies are interlocked by the hardware.  Operands: %0..%8 the
+// columns, %9 = a, %10 = b, %11.. the broadcast lanes OFF+q.
+#define ROTSEQ_FMAC(X, A, Y, L) "v_fmac_f64_dpp %" #X ", %" #A ", %" #Y " row_newbcast:%" #L " row_mask:0xf bank_mask:0xf\n"
+#define ROTSEQ_ROT(L, X, Y) ROTSEQ_FMAC(X, 9, Y, L) ROTSEQ_FMAC(Y, 10, X, L) ROTSEQ_FMAC(X, 9, Y, L)
+#define ROTSEQ_COLS "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]), "+v"(c[7]), "+v"(c[8])
+template <int K, int OFF>
+__device__ __forceinline__ void lift_step(double (&c)[9], double a, double b)
 {
-    asm(ROTSEQ_ROT(0, 1, 0) ROTSEQ_ROT(1, 2, 1) ROTSEQ_ROT(2, 3, 2) ROTSEQ_ROT(3, 4, 3)
-        ROTSEQ_ROT(4, 5, 4) ROTSEQ_ROT(5, 6, 5) ROTSEQ_ROT(6, 7, 6) ROTSEQ_ROT(7, 8, 7)
-        : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
-          "+v"(c[7]), "+v"(c[8])
-        : "v"(a), "v"(b));
+    static_assert(OFF + K <= 16, "broadcast lanes lie in one 16-lane row");
+    if constexpr (K == 8)
+        asm(ROTSEQ_ROT(11, 1, 0) ROTSEQ_ROT(12, 2, 1) ROTSEQ_ROT(13, 3, 2) ROTSEQ_ROT(14, 4, 3)
+            ROTSEQ_ROT(15, 5, 4) ROTSEQ_ROT(16, 6, 5) ROTSEQ_ROT(17, 7, 6) ROTSEQ_ROT(18, 8, 7)
+            : ROTSEQ_COLS
+            : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3), "n"(OFF + 4),
+              "n"(OFF + 5), "n"(OFF + 6), "n"(OFF + 7));
+    else if constexpr (K == 6)
+        asm(ROTSEQ_ROT(11, 1, 0) ROTSEQ_ROT(12, 2, 1) ROTSEQ_ROT(13, 3, 2) ROTSEQ_ROT(14, 4, 3)
+            ROTSEQ_ROT(15, 5, 4) ROTSEQ_ROT(16, 6, 5)
+            : ROTSEQ_COLS
+            : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3), "n"(OFF + 4),
+              "n"(OFF + 5));
+    else
+        asm(ROTSEQ_ROT(11, 1, 0) ROTSEQ_ROT(12, 2, 1) ROTSEQ_ROT(13, 3, 2) ROTSEQ_ROT(14, 4, 3)
+            : ROTSEQ_COLS
+            : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3));
 }
-template <>
-__device__ __forceinline__ void lift_step<6>(double (&c)[9], double a, double b)
-{
-    asm(ROTSEQ_ROT(0, 1, 0) ROTSEQ_ROT(1, 2, 1) ROTSEQ_ROT(2, 3, 2) ROTSEQ_ROT(3, 4, 3)
-        ROTSEQ_ROT(4, 5, 4) ROTSEQ_ROT(5, 6, 5)
-        : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
-          "+v"(c[7]), "+v"(c[8])
-        : "v"(a), "v"(b));
-}
-template <>
-__device__ __forceinline__ void lift_step<4>(double (&c)[9], double a, double b)
-{
-    asm(ROTSEQ_ROT(0, 1, 0) ROTSEQ_ROT(1, 2, 1) ROTSEQ_ROT(2, 3, 2) ROTSEQ_ROT(3, 4, 3)
-        : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
-          "+v"(c[7]), "+v"(c[8])
-        : "v"(a), "v"(b));
-}
+#undef ROTSEQ_COLS
 #undef ROTSEQ_ROT
 #undef ROTSEQ_FMAC
 
@@ -223,6 +242,19 @@ __device__ __forceinline__ void static_for(F &&f)
     if constexpr (Q < N) {
         f(std::integral_constant<int, Q>{});
         static_for<Q + 1, N>(f);
+    }
+}
+
+// Calls f(std::integral_constant<int, J>) for the J == j in [0, N).  In the
+// unrolled step loop j is a constant, so a single call remains.
+template <int N, int J = 0, typename F>
+__device__ __forceinline__ void select_const(int j, F &&f)
+{
+    if constexpr (J < N) {
+        if (j == J)
+            f(std::integral_constant<int, J>{});
+        else
+            select_const<N, J + 1>(j, f);
     }
 }
 
@@ -264,10 +296,11 @@ enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel 
 // Flow control is per column, evaluated once per group of G = 4 steps.  A
 // consumer (LDS input) may read column c once produced > c; a producer (LDS
 // output) may overwrite the slot of column c - RB once consumed > c - RB.
-// Both counters are published once per group and re-read asynchronously
-// (an LDS load issued one group earlier), so a wave only stalls when its
-// neighbour really is behind; when it must wait it waits for extra headroom
-// (kInSlack columns, kOutSlack slots) so the next wait is further away.
+// Both counters advance every step (an LDS atomic add after the slot access)
+// and are re-read asynchronously (an LDS load issued one step before the
+// group), so a wave only stalls when its neighbour really is behind; when it
+// must wait it waits for extra headroom (kInSlack columns, kOutSlack slots)
+// so the next wait is further away.
 //
 // Channel reads and writes are unconditional: columns outside [0, n)
 // travel as data too (zeros, or past n possibly an older finite column of
@@ -295,6 +328,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     typedef __attribute__((address_space(3))) T lds_T;
     const int n = a.n;
     const int lane = threadIdx.x & (kWave - 1);
+    const bool leader = lane == 0;
     const int64_t i0 = (int64_t)tile * kWave;
     const int64_t rows = a.m - i0 < kWave ? a.m - i0 : kWave;
     const uint32_t rowbytes = (uint32_t)(rows * (int64_t)sizeof(T));
@@ -302,13 +336,14 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     const uint64_t tileaddr = a.A + (uint64_t)i0 * sizeof(T);
     const uint64_t ldab = a.ldab;
     int limit = a.spin_limit;
-    int *status = a.status;
+    int timed_out = 0;
 
     __attribute__((address_space(3))) char *lds = (__attribute__((address_space(3))) char *)lds_generic;
     lds_counter *cnt = (lds_counter *)lds;
     lds_T *rings = (lds_T *)(lds + kCounters * sizeof(int));
     lds_counter *prod_in = cnt + (w - 1), *cons_in = cnt + 16 + (w - 1);
     lds_counter *prod_out = cnt + w, *cons_out = cnt + 16 + w;
+    lds_counter *cons_in_v = addr_in_vgpr(cons_in), *prod_out_v = addr_in_vgpr(prod_out);
     lds_T *ring_in = rings + (w - 1) * RB * SLOT + lane;
     lds_T *ring_out = rings + w * RB * SLOT + lane;
     int *flag_in = a.flags + (int64_t)tile * a.nbands + (b - 1);
@@ -316,7 +351,13 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     const int pubmask = a.publish - 1;
 
     // Input columns < in_known exist; the LDS consumer has read columns
-    // < out_known.  in_poll / out_poll: counter values read a group ago.
+    // < out_known.  in_poll / out_poll: counter values read one step (LDS)
+    // or one group (flag) before the group that uses them.
+    //
+    // LDS counters count steps: a producer adds 1 after writing each output
+    // slot (its first kLead steps output columns < 0), a consumer adds 1
+    // after reading each input slot, so both are current to the step.
+    constexpr int kLead = K - 1;
     int in_known = IN == kInFresh ? 0x7fffffff : 0;
     int out_known = 0;
     int in_poll = 0, out_poll = 0;
@@ -335,9 +376,9 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                 const int want = lc + cols + kInSlack;
                 const int need = (want < n ? want : n) - 1;
                 if constexpr (IN == kInLds)
-                    in_known = wait_lds(prod_in, need, limit, status, kWaitLdsIn);
+                    in_known = wait_lds(prod_in, need + kLead, limit, timed_out, kWaitLdsIn) - kLead;
                 else
-                    in_known = wait_flag(flag_in, need, limit, status);
+                    in_known = wait_flag(flag_in, need, limit, timed_out);
             }
         }
     };
@@ -371,39 +412,50 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     int sc = -(K - 1);
     uint64_t sp = tileaddr - (uint64_t)(K - 1) * ldab;
 
-    // Coefficient pipeline: record of step t is loaded into cf[t % kCoefAhead]
-    // kCoefAhead steps before step t.  Lane l loads pair min(l mod 16, K-1);
-    // only lanes l mod 16 < K are ever read.
-    constexpr int kCoefAhead = 8;
-    static_assert(U % kCoefAhead == 0, "coefficient ring must tile the unroll");
+    // Coefficient pipeline: one load brings the records of SPL consecutive
+    // steps (lane l of each row: pair l mod 16 from the first step's record
+    // on; lanes past SPL*K repeat the last pair and are never read).  NL
+    // loads are in flight, so a step's records arrive kAhead steps early.
+    // (FP32 with K = 4 takes two steps per load: with four, the compiler
+    // re-packs the loaded pairs with VALU moves right before their DPP reads.)
+    constexpr int SPL = sizeof(T) == 4 && K == 4 ? 2 : 16 / K;
+    constexpr int NL = 4;
+    constexpr int kAhead = NL * SPL;
+    static_assert(U % kAhead == 0, "coefficient ring must tile the unroll");
+    static_assert(kAhead < kChainCoefPad, "look-ahead must stay inside the identity padding");
     using CL = CoefLane<T>;
     constexpr int kStepBytes = K * (int)sizeof(CoefPair<T>);
     const int q16 = lane & 15;
-    const int cvoff = (q16 < K ? q16 : K - 1) * (int)sizeof(CoefPair<T>);
-    const uint64_t cbase = a.coef + (uint64_t)b * (a.steps + 1 + kCoefAhead) * kStepBytes;
+    const int cvoff = (q16 < SPL * K ? q16 : SPL * K - 1) * (int)sizeof(CoefPair<T>);
+    const uint64_t cbase = a.coef + (uint64_t)b * (a.steps + kChainCoefPad) * kStepBytes;
     const __amdgpu_buffer_rsrc_t crs =
-        make_rsrc(cbase, (uint32_t)((a.steps + 1 + kCoefAhead) * kStepBytes));
+        make_rsrc(cbase, (uint32_t)((a.steps + kChainCoefPad) * kStepBytes));
     int coff = 0;  // byte offset of the record of step t0 (block base)
-    typename CL::bits cf[kCoefAhead];
+    typename CL::bits cf[NL], cur;
 #pragma unroll
-    for (int i = 0; i < kCoefAhead; ++i)
-        cf[i] = CL::load(crs, cvoff, i * kStepBytes);
+    for (int i = 0; i < NL; ++i)
+        cf[i] = CL::load(crs, cvoff, i * SPL * kStepBytes);
     ConstScalars<T> sign = (ConstScalars<T>)a.sign;
     constexpr bool kSign = OUT == kOutFinal && ARITH == kLift;
     T sg = T(1);
     if constexpr (kSign)
         sg = sign[0];
     int blk = 0;
+    // Drain the prologue's loads once: the compiler's wait-count analysis
+    // merges the loop entry with the back edge, and a load still in flight
+    // from the prologue would make it wait for nearly every load at the top
+    // of each group instead of only for the one whose data is used.
+    wait_vmem_at_most<0>();
 
     for (int t0 = 0; t0 < a.steps; t0 += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (u % G == 0) {
-                // Group prologue: fold in the counters read a group ago, make
+                // Group prologue: fold in the counters polled earlier, make
                 // sure this group's G fetches and G slot writes are allowed,
-                // and re-read the counters for the next group.
+                // and re-read the flag for the next group.
                 if constexpr (IN == kInLds || IN == kInWait) {
-                    const int v = uniform(in_poll);
+                    const int v = uniform(in_poll) - (IN == kInLds ? kLead : 0);
                     in_known = v > in_known ? v : in_known;
                 }
                 ensure_in(G);
@@ -411,46 +463,61 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                     const int v = uniform(out_poll);
                     out_known = v > out_known ? v : out_known;
                     if (sc + G > out_known + RB)  // slot of column sc+G-1-RB must be read
-                        out_known = wait_lds(cons_out, sc + G - 1 - RB + kOutSlack, limit, status, kWaitLdsOut);
+                        out_known = wait_lds(cons_out, sc + G - 1 - RB + kOutSlack, limit, timed_out, kWaitLdsOut);
                 }
+                if constexpr (IN == kInWait)
+                    in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (u % G == G - 1) {
+                // Poll the LDS counters one step before the next group needs them.
                 if constexpr (IN == kInLds)
                     in_poll = *prod_in;
-                else if constexpr (IN == kInWait)
-                    in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if constexpr (OUT == kOutLds)
                     out_poll = *cons_out;
             }
-            // This step's coefficients; refill the slot kCoefAhead steps ahead
-            // (records past the last step are identity padding).
-            const typename CL::bits cur = cf[u % kCoefAhead];
-            cf[u % kCoefAhead] = CL::load(crs, cvoff, coff + (u + kCoefAhead) * kStepBytes);
+            // Coefficients of this step (lanes OFF..OFF+K-1 of each row of
+            // `cur`); a new record group replaces the one just taken, kAhead
+            // steps ahead (records past the last step are identity padding).
+            if (u % SPL == 0) {
+                cur = cf[(u / SPL) % NL];
+                cf[(u / SPL) % NL] = CL::load(crs, cvoff, coff + (u + kAhead) * kStepBytes);
+            }
             // Column t+1+D replaces column t-K, finished last step.
             fetch(ring[(u + D + 1) % R], (u + D + 1) % RB);
-            if constexpr (sizeof(T) == 8 && ARITH == kLift) {
-                // c[j] = column t+1-j, j = 0..K (unused operands are dummies).
-                double c[9];
-#pragma unroll
-                for (int j = 0; j < 9; ++j)
-                    c[j] = j <= K ? ring[(u + 1 - j + U) % R] : 0.0;
-                lift_step<K>(c, CL::a(cur), CL::b(cur));
-#pragma unroll
-                for (int j = 0; j <= K; ++j)
-                    ring[(u + 1 - j + U) % R] = c[j];
-            } else {
-                static_for<0, K>([&](auto qc) {
-                    constexpr int q = decltype(qc)::value;
-                    if constexpr (sizeof(T) == 8)
-                        rotate_bcast<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
-                                               CL::a(cur), CL::b(cur));
-                    else
-                        rotate_bcast_pair<ARITH, q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
-                                                    CL::pair(cur));
-                });
+            if constexpr (IN == kInLds) {
+                compiler_fence();
+                lds_inc(cons_in_v, leader);
             }
+            select_const<SPL>(u % SPL, [&](auto jc) {
+                constexpr int OFF = decltype(jc)::value * K;
+                if constexpr (sizeof(T) == 8 && ARITH == kLift) {
+                    // c[j] = column t+1-j, j = 0..K (unused operands are dummies).
+                    double c[9];
+#pragma unroll
+                    for (int j = 0; j < 9; ++j)
+                        c[j] = j <= K ? ring[(u + 1 - j + U) % R] : 0.0;
+                    lift_step<K, OFF>(c, CL::a(cur), CL::b(cur));
+#pragma unroll
+                    for (int j = 0; j <= K; ++j)
+                        ring[(u + 1 - j + U) % R] = c[j];
+                } else {
+                    static_for<0, K>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        if constexpr (sizeof(T) == 8)
+                            rotate_bcast<ARITH, OFF + q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
+                                                         CL::a(cur), CL::b(cur));
+                        else
+                            rotate_bcast_pair<ARITH, OFF + q>(ring[(u - q + U) % R],
+                                                              ring[(u - q + 1 + U) % R], CL::pair(cur));
+                    });
+                }
+            });
             // Column sc = t-K+1 has seen the whole band.
             T val = ring[(u - K + 1 + U) % R];
             if constexpr (OUT == kOutLds) {
                 ring_out[((u - K + 1 + U) % RB) * SLOT] = val;
+                compiler_fence();
+                lds_inc(prod_out_v, leader);
             } else {
                 const int c = sc + (u % G);
                 const bool valid = (unsigned)c < (unsigned)n;
@@ -467,15 +534,9 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                 opaque(sp);
             }
             if (u % G == G - 1) {
-                // Group epilogue: publish progress.
                 sc += G;
                 opaque_i(lc);
                 opaque_i(sc);
-                compiler_fence();
-                if constexpr (IN == kInLds)
-                    *cons_in = lc;
-                if constexpr (OUT == kOutLds)
-                    *prod_out = sc;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -496,6 +557,8 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         wait_vmem_at_most<0>();
         __hip_atomic_store(flag_out, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (timed_out)
+        record_timeout(a.status, timed_out);
 }
 
 template <typename T, int K, int ARITH, int IN>

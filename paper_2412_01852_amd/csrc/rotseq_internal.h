@@ -14,14 +14,18 @@ enum Arith : int { kExact = 1, kFma = 2, kLift = 3 };
 // Sweep kernel families (values of rotseq_opts.kernel after resolving AUTO).
 enum Kernel : int { kMultipass = 1, kChain = 2 };
 
+// Identity records after the last step of each band for the chain kernel;
+// covers its deepest coefficient look-ahead (16 steps) plus one.
+constexpr int kChainCoefPad = 17;
+
 // Shape of one call after dispatch decisions: A is m x n (column-major, lda),
 // the k sequences are cut into `npass` bands of `band` sequences (the last
 // band is padded with identity rotations), and every sweep over the columns
 // takes `steps` wavefront steps (n + band - 1 rounded up to the kernel's
 // unroll length; steps past the last real one are identity).
 // The coefficient buffer holds steps + pad records per band (pad = 1 for the
-// multipass kernel, 9 for the chain kernel): sweeps prefetch records past
-// their last step, which are identity padding.
+// multipass kernel, kChainCoefPad for the chain kernel): sweeps prefetch
+// records past their last step, which are identity padding.
 struct Plan {
     int64_t m, n, k, lda, ldc, lds;
     int kernel;  // Kernel

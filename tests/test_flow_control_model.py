@@ -2,10 +2,14 @@
 
 A producer wave writes columns into a ring of RB slots and a consumer wave
 reads them, both in groups of G columns.  Each side publishes its counter
-(produced / consumed) at the end of a group.  At the start of a group a side
-checks whether the group is allowed; if not, it waits until its neighbour's
-counter reaches the group's need plus extra headroom (IN_SLACK columns for
-the consumer, OUT_SLACK slots for the producer), exactly as the kernel does.
+(produced / consumed) after every column (the kernel's LDS atomic add; the
+older protocol published at the end of a group, still modelled), and polls
+its neighbour's counter at the last step of a group for use at the start of
+the next one (or, in the older protocol, at the start of the previous group).
+At the start of a group a side checks whether the group is allowed; if not,
+it waits until its neighbour's counter reaches the group's need plus extra
+headroom (IN_SLACK columns for the consumer, OUT_SLACK slots for the
+producer), exactly as the kernel does.
 
 The model runs both sides with random relative speeds and checks that the
 pair always finishes (no deadlock), that no column is read before it was
@@ -24,8 +28,12 @@ IN_SLACK = (SLACK + 1) // 2
 OUT_SLACK = SLACK - IN_SLACK
 
 
-def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000):
+def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000, per_step=True):
     """True if producer and consumer both finish, False on deadlock.
+
+    per_step: counters published after every column and polled at the last
+    step of the previous group (the kernel); False: published at group ends
+    and polled at the start of the previous group.
 
     Producer step t outputs column t - k_lag + 1; consumer step t fetches
     column t + d_cons + 1 after a preload of columns 0..d_cons.  Columns
@@ -67,6 +75,9 @@ def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000):
             else:
                 if c_t % G == 0 and c_wait is None:
                     c_known = max(c_known, c_poll)
+                    if not per_step:
+                        c_poll = produced
+                if per_step and c_t % G == G - 1:
                     c_poll = produced
                 if c_t % G == 0 and lc < n and c_known < min(lc + G, n):
                     c_wait = min(lc + G + in_slack, n)
@@ -75,7 +86,7 @@ def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000):
                         assert slot.get(lc % RB) == lc, "read before write"
                     lc += 1
                     c_t += 1
-                    if c_t % G == 0:
+                    if per_step or c_t % G == 0:
                         consumed = lc
                     moved = True
         # --- producer
@@ -85,6 +96,9 @@ def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000):
         if p_wait is None and p_t < total and rng.random() < 0.5:
             if p_t % G == 0:
                 p_known = max(p_known, p_poll)
+                if not per_step:
+                    p_poll = consumed
+            if per_step and p_t % G == G - 1:
                 p_poll = consumed
             if p_t % G == 0 and sc + G > p_known + RB:
                 p_wait = sc + G - RB + out_slack
@@ -95,7 +109,7 @@ def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000):
                     slot[sc % RB] = sc
                 sc += 1
                 p_t += 1
-                if p_t % G == 0:
+                if per_step or p_t % G == 0:
                     produced = sc
                 moved = True
         c_stuck = c_wait is not None and produced < c_wait
@@ -107,17 +121,26 @@ def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000):
     return False
 
 
+@pytest.mark.parametrize("per_step", [True, False])
 @pytest.mark.parametrize("seed", range(30))
 @pytest.mark.parametrize("k_lag,d_cons", [(6, 1), (4, 3), (8, 7), (6, 9)])
 @pytest.mark.parametrize("n", [5, 37, 300])
-def test_protocol_finishes(seed, k_lag, d_cons, n):
-    assert simulate(n, k_lag, d_cons, IN_SLACK, OUT_SLACK, seed)
+def test_protocol_finishes(seed, k_lag, d_cons, n, per_step):
+    assert simulate(n, k_lag, d_cons, IN_SLACK, OUT_SLACK, seed, per_step=per_step)
 
 
-def test_model_detects_deadlock_with_too_much_slack():
+@pytest.mark.parametrize("per_step", [True, False])
+def test_model_detects_deadlock_with_too_much_slack(per_step):
     """Slack 8 + 7 with G = 4 (above the bound) deadlocks once a side decides
     to wait on a stale counter: the model must find it."""
-    results = [simulate(300, 6, 1, 8, 7, seed) for seed in range(60)]
+    results = [simulate(300, 8, 7, 8, 7, seed, per_step=per_step) for seed in range(60)]
+    assert not all(results)
+
+
+def test_bound_is_tight_for_per_step_protocol():
+    """One slot of slack above RB + 1 - 2G (6 + 4) already deadlocks."""
+    assert 6 + 4 == RB + 2 - 2 * G
+    results = [simulate(300, 8, 7, 6, 4, seed) for seed in range(60)]
     assert not all(results)
 
 

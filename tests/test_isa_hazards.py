@@ -34,9 +34,10 @@ def chain_asm(tmp_path_factory):
     if not shutil.which(HIPCC) and not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
     out = tmp_path_factory.mktemp("isa") / "chain.s"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "--cuda-device-only", "-S",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           f"-I{ROOT}/include", f"-I{CSRC}", os.path.join(CSRC, "rotseq_chain.hip"), "-o", str(out)]
+    from paper_2412_01852_amd import build
+    # the library's own flags, so the scanned code is the code that runs
+    cmd = [HIPCC, *build.FLAGS, "--cuda-device-only", "-S",
+           os.path.join(CSRC, "rotseq_chain.hip"), "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True)
     return out.read_text()
 
