@@ -37,6 +37,7 @@ WORKLOADS = {
     **{f"tall-f32-32768x4096-k{k}": dict(m=32768, n=4096, k=k, dtype="f32", seed=3 + k)
        for k in (1, 8, 32, 128)},
 }
+BATCHED = {"batched-f64-512": dict(count=512, seed=4, dtype="f64")}
 DEFAULT = "plain-f64-10240-k192"
 
 
@@ -97,12 +98,103 @@ def cpu_baseline(pb, dtype, target_s=15.0):
                       f"({dt:.1f} s, FP64 oracle, row-partitioned threads)"}
 
 
+def bench_batched(args):
+    """The uneven batch in one plan, replayed from a HIP graph.
+
+    One step = one graph replay = preparation + sweep of every problem.  The
+    loop of single calls on the same stream is timed beside it for context.
+    """
+    import torch
+    import paper_2412_01852_amd as rs
+    from paper_2412_01852_amd.inputs import batched_problems
+
+    wl = BATCHED[args.workload]
+    tdt = torch.float64 if wl["dtype"] == "f64" else torch.float32
+    pbs = batched_problems(wl["count"], seed=wl["seed"])
+    dev = [(rs.device_colmajor(p.A, "cuda:0", tdt), rs.device_colmajor(p.C, "cuda:0", tdt),
+            rs.device_colmajor(p.S, "cuda:0", tdt)) for p in pbs]
+    batch = rs.Batch(dev)
+    batch.tune(reps=2)
+    info = batch.info()
+    stream = torch.cuda.Stream()
+    for _ in range(max(1, args.warmup)):
+        batch.execute(stream=stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            batch.execute(stream=stream)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_dev = e0.elapsed_time(e1) / args.steps
+    # The same problems as a loop of single calls on one stream (context).
+    loops = max(1, min(5, args.steps))
+    torch.cuda.synchronize()
+    l0 = time.perf_counter()
+    for _ in range(loops):
+        for A, C, S in dev:
+            rs.rotseq(A, C, S, stream=stream)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - l0) * 1e3 / loops
+    flops, nbytes = info["flops"], info["bytes"]
+    esize = 8 if wl["dtype"] == "f64" else 4
+    peak = PEAK_TFLOPS[wl["dtype"]]
+    bound_ms = max(flops / (peak * 1e12), nbytes / (HBM_GBS * 1e9)) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(flops / (ms_step * 1e-3) / 1e9, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl["dtype"],
+        "data": "synthetic (n log-uniform [64,2048], m=n, k in {8,16,32,64}; A iid N(0,1), "
+                "angles iid U[0,2pi), seeded PCG64 per problem)",
+        "config": {"workload": args.workload, "problems": info["count"], "band": info["band"],
+                   "waves_per_workgroup": info["waves"], "workgroups": info["workgroups"],
+                   "flops": flops, "compulsory_bytes": nbytes, "graph": True,
+                   "parallelism": "single GPU"},
+        "roofline": {
+            "bound": "alu" if flops / (peak * 1e12) >= nbytes / (HBM_GBS * 1e9) else "hbm",
+            "achieved": round(flops / (ms_dev * 1e-3) / 1e12, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(bound_ms / ms_dev, 4),
+            "traffic": None,
+            "kernel": "batch (prep + sweep, graph replay)",
+            "kernel_ms": round(ms_dev, 4),
+            "bound_ms": round(bound_ms, 4),
+            "hbm_gbs_achieved": round(nbytes / (ms_dev * 1e-3) / 1e9, 1),
+            "element_bytes": esize,
+        },
+        "loop_of_single_calls_ms": round(loop_ms, 4),
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -110,6 +202,9 @@ def main():
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(rows shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         return 2
+
+    if args.workload in BATCHED:
+        return bench_batched(args)
 
     import numpy as np
     import torch

@@ -177,6 +177,96 @@ int rotseq_profile_read(rotseq_profile *out, int reset);
  */
 int rotseq_device_status(int reset);
 
+/*
+ * Batches (many independent problems in one launch sequence).
+ *
+ * A batch is a host array of problem descriptors.  Each entry is a full
+ * rotseq_d/rotseq_s call (same arguments, same semantics, same layouts);
+ * the entries are independent and their A matrices must not overlap each
+ * other (C and S may be shared).  All pointers are device pointers owned by
+ * the caller.  Entries with nothing to do (m == 0, n <= 1 or k == 0) are
+ * skipped.  The result equals a loop of rotseq_d/rotseq_s over the entries,
+ * up to rounding (Section 1: each entry is Algorithm 2 on its own matrix).
+ *
+ * An invalid entry makes the call return -(1000*(idx+1) + argpos), where idx
+ * is the 0-based entry and argpos the 1-based position of the offending
+ * field in the rotseq_d argument list (1 m, 2 n, 3 k, 4 A, 5 lda, 6 C, 7 ldc,
+ * 8 S, 9 lds); argpos 4 also flags an A that overlaps another entry's A.
+ * count < 0 returns -1; probs == NULL with count > 0 returns -2.
+ */
+typedef struct rotseq_problem_d {
+    int64_t m, n, k;
+    double *A;
+    int64_t lda;
+    const double *C;
+    int64_t ldc;
+    const double *S;
+    int64_t lds;
+} rotseq_problem_d;
+
+typedef struct rotseq_problem_s {
+    int64_t m, n, k;
+    float *A;
+    int64_t lda;
+    const float *C;
+    int64_t ldc;
+    const float *S;
+    int64_t lds;
+} rotseq_problem_s;
+
+/*
+ * rotseq_batched_d / rotseq_batched_s: one-shot batch.  Builds a batch plan,
+ * runs it on `stream`, waits for the stream and frees the plan, so it blocks
+ * until the batch is done.  For repeated batches or HIP graph capture use
+ * the plan calls below.
+ */
+int rotseq_batched_d(int32_t count, const rotseq_problem_d *probs, hipStream_t stream);
+int rotseq_batched_s(int32_t count, const rotseq_problem_s *probs, hipStream_t stream);
+
+/*
+ * Batch plans.  rotseq_batch_create_{d,s} validates the entries, sorts them
+ * by decreasing work (longest chains are dispatched first), allocates and
+ * fills the plan's device memory (descriptors and workspace; this call
+ * synchronizes the device) and keeps the pointers: later executions use the
+ * same A, C and S buffers, whose contents may change between executions.
+ * `opts` as for rotseq_ex_d (kernel must be AUTO or CHAIN; band 4, 6 or 8;
+ * waves 0 = planned); NULL for defaults.
+ *
+ * rotseq_batch_execute launches the whole batch on `stream`: one launch per
+ * preparation stage over all entries, then one sweep launch over all
+ * entries.  It allocates nothing and never synchronizes, so it can be
+ * captured into a HIP graph; executions of one plan must not overlap.
+ *
+ * rotseq_batch_tune times the batch on `stream` for each candidate number of
+ * waves per workgroup (`reps` timed executions each, after one warm-up) and
+ * keeps the fastest.  It applies the rotations (1 + reps) times per
+ * candidate, so the A buffers change; it blocks until done.
+ *
+ * rotseq_batch_destroy frees the plan (waits for the device first).
+ */
+typedef struct rotseq_batch rotseq_batch;
+
+typedef struct rotseq_batch_info {
+    int32_t count;      /* entries with work                                */
+    int32_t band;       /* sequences per band                               */
+    int32_t waves;      /* waves (bands) per workgroup of the sweep launch  */
+    int32_t reserved;
+    int64_t workgroups; /* workgroups of the sweep launch                   */
+    int64_t waves_total;/* band-waves over all entries                      */
+    double flops;       /* 6 m (n-1) k summed over entries                  */
+    double bytes;       /* compulsory bytes: w (2 m n + 2 (n-1) k) summed   */
+    size_t device_bytes;/* device memory held by the plan                   */
+} rotseq_batch_info;
+
+int rotseq_batch_create_d(int32_t count, const rotseq_problem_d *probs, const rotseq_opts *opts,
+                          rotseq_batch **out);
+int rotseq_batch_create_s(int32_t count, const rotseq_problem_s *probs, const rotseq_opts *opts,
+                          rotseq_batch **out);
+int rotseq_batch_execute(rotseq_batch *batch, hipStream_t stream);
+int rotseq_batch_tune(rotseq_batch *batch, hipStream_t stream, int32_t reps);
+int rotseq_batch_info_get(const rotseq_batch *batch, rotseq_batch_info *info);
+int rotseq_batch_destroy(rotseq_batch *batch);
+
 /* Static description of a return code. */
 const char *rotseq_strerror(int code);
 

@@ -36,6 +36,21 @@ class Profile(ctypes.Structure):
                 ("sweep_ms_max", ctypes.c_double)]
 
 
+class Problem(ctypes.Structure):
+    """rotseq_problem_d / rotseq_problem_s (same layout: pointers are void*)."""
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("S", ctypes.c_void_p), ("lds", ctypes.c_int64)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workgroups", ctypes.c_int64),
+                ("waves_total", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+
 def profile_enable(on=True):
     _load().rotseq_profile_enable(1 if on else 0)
 
@@ -88,6 +103,19 @@ def _load():
     lib.rotseq_profile_enable.argtypes = [i32]
     lib.rotseq_profile_read.restype = i32
     lib.rotseq_profile_read.argtypes = [ctypes.POINTER(Profile), i32]
+    pp = ctypes.POINTER(Problem)
+    for name in ("rotseq_batched_d", "rotseq_batched_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, [ctypes.c_int32, pp, vp]
+    for name in ("rotseq_batch_create_d", "rotseq_batch_create_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, [ctypes.c_int32, pp, ctypes.POINTER(Options),
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.rotseq_batch_execute.restype, lib.rotseq_batch_execute.argtypes = i32, [vp, vp]
+    lib.rotseq_batch_tune.restype, lib.rotseq_batch_tune.argtypes = i32, [vp, vp, ctypes.c_int32]
+    lib.rotseq_batch_info_get.restype = i32
+    lib.rotseq_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    lib.rotseq_batch_destroy.restype, lib.rotseq_batch_destroy.argtypes = i32, [vp]
     _lib = lib
     return lib
 
@@ -193,3 +221,91 @@ def device_colmajor(view, device="cuda", dtype=None):
 def host_colmajor(t):
     """Device column-major (m, n) tensor -> numpy float64 (m, n) array."""
     return t.detach().to("cpu", dtype=__import__("torch").float64).numpy()
+
+
+def _problems(items):
+    """(A, C, S) device tensor triples -> (ctypes Problem array, is_double)."""
+    import torch
+    arr = (Problem * max(len(items), 1))()
+    dbl = None
+    for i, (A, C, S) in enumerate(items):
+        if A.dtype not in (torch.float64, torch.float32) or C.dtype != A.dtype or S.dtype != A.dtype:
+            raise TypeError(f"problem {i}: A, C, S must share a float64/float32 dtype")
+        if dbl is None:
+            dbl = A.dtype == torch.float64
+        elif dbl != (A.dtype == torch.float64):
+            raise TypeError("all problems of a batch must share a dtype")
+        m, n = A.shape
+        ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+        arr[i] = Problem(m, n, C.shape[1], ptr(A), _ld(A, "A"), ptr(C), _ld(C, "C"),
+                         ptr(S), _ld(S, "S"))
+    return arr, bool(dbl) if dbl is not None else True
+
+
+def _stream(stream, device=None):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def batched(items, stream=None):
+    """One-shot batch: A_i <- A_i * prod G for every (A_i, C_i, S_i); blocks."""
+    arr, dbl = _problems(items)
+    lib = _load()
+    fn = lib.rotseq_batched_d if dbl else lib.rotseq_batched_s
+    rc = fn(len(items), arr, _stream(stream))
+    if rc != 0:
+        raise RotseqError(rc, "batched")
+
+
+class Batch:
+    """A batch plan (rotseq_batch_*): create once, execute many times.
+
+    ``execute`` only launches kernels (no allocation, no synchronization), so
+    it can be captured into a CUDA/HIP graph.  The tensors must stay alive
+    while the plan exists.
+    """
+
+    def __init__(self, items, opts=None):
+        arr, dbl = _problems(items)
+        self._keep = list(items)
+        self._handle = ctypes.c_void_p()
+        lib = _load()
+        fn = lib.rotseq_batch_create_d if dbl else lib.rotseq_batch_create_s
+        rc = fn(len(items), arr, _opts(opts), ctypes.byref(self._handle))
+        if rc != 0:
+            raise RotseqError(rc, "batch_create")
+
+    def execute(self, stream=None):
+        rc = _load().rotseq_batch_execute(self._handle, _stream(stream))
+        if rc != 0:
+            raise RotseqError(rc, "batch_execute")
+
+    def tune(self, reps=3, stream=None):
+        rc = _load().rotseq_batch_tune(self._handle, _stream(stream), int(reps))
+        if rc != 0:
+            raise RotseqError(rc, "batch_tune")
+
+    def info(self):
+        out = BatchInfo()
+        rc = _load().rotseq_batch_info_get(self._handle, ctypes.byref(out))
+        if rc != 0:
+            raise RotseqError(rc, "batch_info")
+        return {f: getattr(out, f) for f, _ in BatchInfo._fields_ if f != "reserved"}
+
+    def close(self):
+        if self._handle:
+            _load().rotseq_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

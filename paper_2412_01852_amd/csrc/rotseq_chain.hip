@@ -573,18 +573,12 @@ __device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b
         bandwave<T, K, ARITH, IN, kOutFinal>(a, tile, b, w, lds);
 }
 
+// Workgroup g of a problem's chain grid: its waves take the (tile, band)
+// units g*W .. g*W+W-1 in tile-major order.
 template <typename T, int K, int ARITH>
-__global__ __launch_bounds__(1024) void sweep_chain(ChainArgs a)
+__device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char *lds)
 {
-    extern __shared__ __align__(16) char lds[];
-    // Counters start at 0; rings start as zeros so that a column slot read
-    // before its first write holds a finite value.
-    for (uint32_t i = threadIdx.x; i < a.lds_words; i += blockDim.x)
-        ((int *)lds)[i] = 0;
-    __syncthreads();
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int p = (int)blockIdx.x;
-    const int g = a.remap ? (p & 7) * (a.nwg >> 3) + (p >> 3) : p;
     const int64_t idx = (int64_t)g * a.waves + w;
     const int64_t total = (int64_t)a.tiles * a.nbands;
     if (idx >= total)
@@ -602,6 +596,72 @@ __global__ __launch_bounds__(1024) void sweep_chain(ChainArgs a)
         bandwave_out<T, K, ARITH, kInFresh>(a, tile, b, w, lds, out);
     else
         bandwave_out<T, K, ARITH, kInWait>(a, tile, b, w, lds, out);
+}
+
+// Zeroes the workgroup's LDS: counters start at 0, and rings start as zeros
+// so that a column slot read before its first write holds a finite value.
+__device__ __forceinline__ void zero_lds(char *lds, uint32_t words)
+{
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x)
+        ((int *)lds)[i] = 0;
+    __syncthreads();
+}
+
+template <typename T, int K, int ARITH>
+__global__ __launch_bounds__(1024) void sweep_chain(ChainArgs a)
+{
+    extern __shared__ __align__(16) char lds[];
+    zero_lds(lds, a.lds_words);
+    const int p = (int)blockIdx.x;
+    const int g = a.remap ? (p & 7) * (a.nwg >> 3) + (p >> 3) : p;
+    chain_workgroup<T, K, ARITH>(a, g, lds);
+}
+
+// A batch in one launch: workgroup ranges of the items follow each other in
+// item order (longest chains first, so the dispatcher starts them early);
+// a workgroup finds its item by binary search and runs as in sweep_chain.
+// Workgroups still only wait for lower-numbered ones of their own item.
+struct BatchChainArgs {
+    const BatchItem *items;
+    int count, waves, publish, spin_limit;
+    uint32_t lds_words;
+    int *status;
+};
+
+template <typename T, int K, int ARITH>
+__global__ __launch_bounds__(1024) void sweep_chain_batch(BatchChainArgs ba)
+{
+    extern __shared__ __align__(16) char lds[];
+    zero_lds(lds, ba.lds_words);
+    const int64_t g = blockIdx.x;
+    int lo = 0, hi = ba.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ba.items[mid].off_wg <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchItem &it = ba.items[lo];
+    ChainArgs a;
+    a.A = (uint64_t)it.A;
+    a.ldab = (uint64_t)it.lda * sizeof(T);
+    a.m = it.m;
+    a.n = (int)it.n;
+    a.steps = it.steps;
+    a.nbands = it.npass;
+    a.tiles = it.tiles;
+    a.waves = ba.waves;
+    a.nwg = 0;
+    a.remap = 0;
+    a.publish = ba.publish;
+    a.spin_limit = ba.spin_limit;
+    a.lds_words = ba.lds_words;
+    a.coef = (uint64_t)it.coef;
+    a.sign = (uint64_t)it.sign;
+    a.flags = it.flags;
+    a.status = ba.status;
+    chain_workgroup<T, K, ARITH>(a, (int)(g - it.off_wg), lds);
 }
 
 template <typename T, int K, int ARITH>
@@ -629,6 +689,43 @@ hipError_t go_chain(const Plan &p, T *A, const char *ws, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename T, int K, int ARITH>
+hipError_t go_chain_batch(const BatchLaunch &b, hipStream_t st)
+{
+    BatchChainArgs a;
+    a.items = b.items;
+    a.count = b.count;
+    a.waves = b.waves;
+    a.publish = b.publish;
+    a.spin_limit = b.spin_limit;
+    a.lds_words = (uint32_t)(b.lds_bytes / 4);
+    a.status = b.status;
+    sweep_chain_batch<T, K, ARITH><<<(unsigned)b.nwg, b.waves * kWave, b.lds_bytes, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, int ARITH>
+hipError_t chain_batch_arith(const BatchLaunch &b, hipStream_t st)
+{
+    switch (b.band) {
+    case 4: return go_chain_batch<T, 4, ARITH>(b, st);
+    case 6: return go_chain_batch<T, 6, ARITH>(b, st);
+    case 8: return go_chain_batch<T, 8, ARITH>(b, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t chain_batch_t(const BatchLaunch &b, hipStream_t st)
+{
+    switch (b.arith) {
+    case kExact: return chain_batch_arith<T, kExact>(b, st);
+    case kFma: return chain_batch_arith<T, kFma>(b, st);
+    case kLift: return chain_batch_arith<T, kLift>(b, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int ARITH>
 hipError_t chain_arith(const Plan &p, T *A, const char *ws, hipStream_t st)
 {
@@ -652,9 +749,10 @@ hipError_t chain_t(const Plan &p, T *A, const char *ws, hipStream_t st)
 }
 
 template <typename T>
-const void *chain_kernel_fn(int band, int arith)
+const void *chain_kernel_fn(int band, int arith, bool batch)
 {
-#define ROTSEQ_CHAIN_FN(KK, AA) (const void *)&sweep_chain<T, KK, AA>
+#define ROTSEQ_CHAIN_FN(KK, AA) \
+    (batch ? (const void *)&sweep_chain_batch<T, KK, AA> : (const void *)&sweep_chain<T, KK, AA>)
     if (band == 4)
         return arith == kExact ? ROTSEQ_CHAIN_FN(4, kExact)
                : arith == kFma ? ROTSEQ_CHAIN_FN(4, kFma)
@@ -683,10 +781,21 @@ size_t chain_lds_bytes(int band, int waves, int esize)
     return kCounters * sizeof(int) + (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
 }
 
-hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks)
+hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,
+                           bool batch)
 {
-    const void *fn = esize == 8 ? chain_kernel_fn<double>(band, arith) : chain_kernel_fn<float>(band, arith);
+    const void *fn = esize == 8 ? chain_kernel_fn<double>(band, arith, batch)
+                                : chain_kernel_fn<float>(band, arith, batch);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, waves * kWave, lds);
+}
+
+hipError_t launch_chain_batch(const BatchLaunch &b, hipStream_t stream)
+{
+    if (b.count <= 0 || b.nwg <= 0)
+        return hipSuccess;
+    if (b.esize == 8)
+        return chain_batch_t<double>(b, stream);
+    return chain_batch_t<float>(b, stream);
 }
 
 hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stream)

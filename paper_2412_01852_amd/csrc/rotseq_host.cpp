@@ -387,6 +387,30 @@ int run(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C, int64_t 
 }
 
 }  // namespace
+
+int check_problem(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *C,
+                  int64_t ldc, const void *S, int64_t lds)
+{
+    return check_args(m, n, k, A, lda, C, ldc, S, lds);
+}
+
+bool resolve_opts(const rotseq_opts *opts, int &arith, int &band, int &kernel)
+{
+    return resolve(opts, arith, band, kernel);
+}
+
+int device_query(int *cus, size_t *max_lds, int **status)
+{
+    DeviceInfo d;
+    const int rc = device_info(d);
+    if (rc)
+        return rc;
+    *cus = d.cus;
+    *max_lds = d.max_lds;
+    *status = d.status;
+    return ROTSEQ_SUCCESS;
+}
+
 }  // namespace rotseq
 
 using namespace rotseq;

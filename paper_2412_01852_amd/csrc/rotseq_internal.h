@@ -44,6 +44,40 @@ struct Plan {
     size_t off_coef, off_negmask, off_parity, off_sign, off_flags, total;
 };
 
+// One problem of a batch, as the batched kernels read it from device memory.
+// The batched launches concatenate the problems' index spaces; the off_*
+// fields are each problem's first index in the concatenation (ascending in
+// item order), so a thread finds its problem by binary search.
+struct BatchItem {
+    void *A;
+    const void *C, *S;
+    int64_t lda, ldc, lds, m, n, k;
+    int npass, steps, tiles, pad;
+    uint64_t *negmask;
+    uint8_t *parity;
+    void *sign;  // T[n]
+    void *coef;  // CoefPair<T>[npass * (steps + pad) * band]
+    int *flags;  // int[tiles * npass]
+    int64_t off_negmask, off_parity, off_sign, off_coef, off_flags, off_wg;
+};
+
+// Launch parameters shared by all items of a batch.
+struct BatchLaunch {
+    int count;         // items
+    int esize, arith, band, waves, publish, spin_limit;
+    size_t lds_bytes;
+    int64_t total_negmask, total_parity, total_sign, total_coef, total_flags, nwg;
+    const BatchItem *items;  // device copy, `count` entries
+    int *status;
+};
+
+hipError_t launch_prep_batch(const BatchLaunch &b, hipStream_t stream);
+// Host helpers of rotseq_host.cpp shared with the batch runtime.
+int check_problem(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *C,
+                  int64_t ldc, const void *S, int64_t lds);
+int device_query(int *cus, size_t *max_lds, int **status);
+hipError_t launch_chain_batch(const BatchLaunch &b, hipStream_t stream);
+
 // Fills the shape-only fields of `p` (kernel, band, npass, steps, unroll,
 // workspace offsets) from its shape and the requested kernel and band
 // (0 = auto).  Returns false for unsupported requests.  Host-only.
@@ -57,7 +91,8 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish);
 int unroll_for_band(int band);
 int chain_unroll(int band);
 size_t chain_lds_bytes(int band, int waves, int esize);
-hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks);
+hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,
+                           bool batch = false);
 hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stream);
 
 // Launchers (rotseq_kernels.hip).  All are asynchronous on `stream` and

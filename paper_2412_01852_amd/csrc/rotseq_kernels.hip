@@ -211,12 +211,9 @@ __device__ __forceinline__ uint64_t low_bits(int q) { return q >= 64 ? ~0ull : (
 
 // negmask[pass*(n-1) + j] bit q = [C(j, pass*K + q) < 0].
 template <typename T>
-__global__ void prep_negmask(const T *__restrict__ C, int64_t ldc, int64_t n1, int64_t k, int K,
-                             int npass, uint64_t *__restrict__ negmask)
+__device__ __forceinline__ uint64_t negmask_elem(const T *__restrict__ C, int64_t ldc, int64_t n1,
+                                                 int64_t k, int K, int64_t idx)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)npass * n1)
-        return;
     const int64_t pass = idx / n1, j = idx - pass * n1;
     uint64_t mask = 0;
     for (int q = 0; q < K; ++q) {
@@ -224,17 +221,14 @@ __global__ void prep_negmask(const T *__restrict__ C, int64_t ldc, int64_t n1, i
         if (p < k && C[j + p * ldc] < T(0))
             mask |= 1ull << q;
     }
-    negmask[idx] = mask;
+    return mask;
 }
 
 // parity[pass*(n-1) + j] = parity of the negations by pair j in bands < pass,
 // for pass = 0 .. npass (the last row is the total).
-__global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
-                            uint8_t *__restrict__ parity)
+__device__ __forceinline__ void parity_elem(const uint64_t *__restrict__ negmask, int64_t n1,
+                                            int npass, uint8_t *__restrict__ parity, int64_t j)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n1)
-        return;
     unsigned acc = 0;
     for (int pass = 0; pass < npass; ++pass) {
         parity[(int64_t)pass * n1 + j] = (uint8_t)acc;
@@ -245,28 +239,22 @@ __global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, in
 
 // sign[c] = (-1)^(negations of column c by pairs c-1 and c over all bands).
 template <typename T>
-__global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__restrict__ sign)
+__device__ __forceinline__ T sign_elem(const uint8_t *__restrict__ total, int64_t n, int64_t c)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n)
-        return;
     const unsigned f = (c > 0 ? total[c - 1] : 0u) ^ (c + 1 < n ? total[c] : 0u);
-    sign[c] = f ? T(-1) : T(1);
+    return f ? T(-1) : T(1);
 }
 
 // coef[(pass*(steps+pad) + t)*K + q] = coefficients of rotation (t-q, pass*K+q),
 // or the identity where that rotation does not exist (t >= steps is always
 // identity padding).
 template <typename T>
-__global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S,
-                          int64_t lds, int64_t n1, int64_t k, int K, int steps, int pad, int npass,
-                          int arith, const uint64_t *__restrict__ negmask,
-                          const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
+__device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_t ldc,
+                                                 const T *__restrict__ S, int64_t lds, int64_t n1,
+                                                 int64_t k, int K, int steps, int pad, int arith,
+                                                 const uint64_t *__restrict__ negmask,
+                                                 const uint8_t *__restrict__ parity, int64_t idx)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)npass * (steps + pad) * K;
-    if (idx >= total)
-        return;
     const int q = (int)(idx % K);
     const int64_t t = (idx / K) % (steps + pad);
     const int64_t pass = idx / ((int64_t)K * (steps + pad));
@@ -302,7 +290,48 @@ __global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restr
         out.a = arith == kLift ? T(0) : T(1);
         out.b = T(0);
     }
-    coef[idx] = out;
+    return out;
+}
+
+template <typename T>
+__global__ void prep_negmask(const T *__restrict__ C, int64_t ldc, int64_t n1, int64_t k, int K,
+                             int npass, uint64_t *__restrict__ negmask)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npass * n1)
+        return;
+    negmask[idx] = negmask_elem(C, ldc, n1, k, K, idx);
+}
+
+__global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
+                            uint8_t *__restrict__ parity)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n1)
+        return;
+    parity_elem(negmask, n1, npass, parity, j);
+}
+
+template <typename T>
+__global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__restrict__ sign)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n)
+        return;
+    sign[c] = sign_elem<T>(total, n, c);
+}
+
+template <typename T>
+__global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S,
+                          int64_t lds, int64_t n1, int64_t k, int K, int steps, int pad, int npass,
+                          int arith, const uint64_t *__restrict__ negmask,
+                          const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)npass * (steps + pad) * K;
+    if (idx >= total)
+        return;
+    coef[idx] = coef_elem(C, ldc, S, lds, n1, k, K, steps, pad, arith, negmask, parity, idx);
 }
 
 __global__ void prep_zero(int *__restrict__ p, int64_t count)
@@ -310,6 +339,68 @@ __global__ void prep_zero(int *__restrict__ p, int64_t count)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count)
         p[i] = 0;
+}
+
+// ------------------------------------------------------------ batched prep
+//
+// One launch per stage covers every problem of a batch: the stage's index
+// space is the concatenation of the problems' spaces, and each thread finds
+// its problem by binary search over the items' first indices.
+
+enum BatchStage : int { kStageNegmask, kStageParity, kStageSign, kStageCoef, kStageFlags };
+
+template <int STAGE>
+__device__ __forceinline__ int64_t stage_off(const BatchItem &it)
+{
+    if constexpr (STAGE == kStageNegmask)
+        return it.off_negmask;
+    else if constexpr (STAGE == kStageParity)
+        return it.off_parity;
+    else if constexpr (STAGE == kStageSign)
+        return it.off_sign;
+    else if constexpr (STAGE == kStageCoef)
+        return it.off_coef;
+    else
+        return it.off_flags;
+}
+
+// Last item whose first index is <= idx (items are in ascending offset order).
+template <int STAGE>
+__device__ __forceinline__ int find_item(const BatchItem *__restrict__ items, int count, int64_t idx)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (stage_off<STAGE>(items[mid]) <= idx)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int STAGE>
+__global__ void prep_batch(const BatchItem *__restrict__ items, int count, int64_t total, int K,
+                           int arith)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total)
+        return;
+    const BatchItem &it = items[find_item<STAGE>(items, count, idx)];
+    const int64_t i = idx - stage_off<STAGE>(it);
+    const int64_t n1 = it.n - 1;
+    if constexpr (STAGE == kStageNegmask)
+        it.negmask[i] = negmask_elem((const T *)it.C, it.ldc, n1, it.k, K, i);
+    else if constexpr (STAGE == kStageParity)
+        parity_elem(it.negmask, n1, it.npass, it.parity, i);
+    else if constexpr (STAGE == kStageSign)
+        ((T *)it.sign)[i] = sign_elem<T>(it.parity + (int64_t)it.npass * n1, it.n, i);
+    else if constexpr (STAGE == kStageCoef)
+        ((CoefPair<T> *)it.coef)[i] = coef_elem((const T *)it.C, it.ldc, (const T *)it.S, it.lds, n1,
+                                                it.k, K, it.steps, it.pad, arith, it.negmask,
+                                                it.parity, i);
+    else
+        it.flags[i] = 0;
 }
 
 inline unsigned blocks_for(int64_t count, int threads) { return (unsigned)((count + threads - 1) / threads); }
@@ -336,6 +427,30 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
     }
     prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.ldc, S, p.lds, n1, p.k, p.band, p.steps,
                                                     p.pad, p.npass, p.arith, negmask, parity, coef);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t prep_batch_t(const BatchLaunch &b, hipStream_t st)
+{
+    constexpr int B = 256;
+    if (b.arith == kLift) {
+        if (b.total_negmask > 0)
+            prep_batch<T, kStageNegmask><<<blocks_for(b.total_negmask, B), B, 0, st>>>(
+                b.items, b.count, b.total_negmask, b.band, b.arith);
+        if (b.total_parity > 0)
+            prep_batch<T, kStageParity><<<blocks_for(b.total_parity, B), B, 0, st>>>(
+                b.items, b.count, b.total_parity, b.band, b.arith);
+        if (b.total_sign > 0)
+            prep_batch<T, kStageSign><<<blocks_for(b.total_sign, B), B, 0, st>>>(
+                b.items, b.count, b.total_sign, b.band, b.arith);
+    }
+    if (b.total_flags > 0)
+        prep_batch<T, kStageFlags><<<blocks_for(b.total_flags, B), B, 0, st>>>(
+            b.items, b.count, b.total_flags, b.band, b.arith);
+    if (b.total_coef > 0)
+        prep_batch<T, kStageCoef><<<blocks_for(b.total_coef, B), B, 0, st>>>(
+            b.items, b.count, b.total_coef, b.band, b.arith);
     return hipGetLastError();
 }
 
@@ -382,6 +497,15 @@ hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws, hi
     if (p.esize == 8)
         return prep_t<double>(p, (const double *)C, (const double *)S, (char *)ws, stream);
     return prep_t<float>(p, (const float *)C, (const float *)S, (char *)ws, stream);
+}
+
+hipError_t launch_prep_batch(const BatchLaunch &b, hipStream_t stream)
+{
+    if (b.count <= 0)
+        return hipSuccess;
+    if (b.esize == 8)
+        return prep_batch_t<double>(b, stream);
+    return prep_batch_t<float>(b, stream);
 }
 
 hipError_t launch_sweep(const Plan &p, void *A, const void *ws, hipStream_t stream)

@@ -81,3 +81,50 @@ def test_workspace_bytes():
     assert big >= 12 * 10255 * 16 * 16
     assert rs.workspace_bytes("float64", 64, 100, 16, {"band": 3}) == 0
     assert rs.workspace_bytes("float64", 64, 100, 16, {"arith": 9}) == 0
+
+
+def _problem(m, n, k, A, lda=None, ldc=None, lds=None, C=0x2000000, S=0x3000000):
+    n1 = max(1, n - 1)
+    return rs.Problem(m, n, k, A, lda if lda is not None else max(1, m),
+                      C, ldc if ldc is not None else n1, S, lds if lds is not None else n1)
+
+
+def _create(probs, count=None):
+    lib = rs._lib._load()
+    arr = (rs.Problem * max(1, len(probs)))(*probs)
+    h = ctypes.c_void_p()
+    n = len(probs) if count is None else count
+    return lib.rotseq_batch_create_d(n, arr if probs else None, None, ctypes.byref(h))
+
+
+def test_batch_rejects_bad_count_and_null_array():
+    assert _create([], count=-1) == -1
+    assert _create([], count=3) == -2
+
+
+@pytest.mark.parametrize("field,value,argpos", [
+    ("m", -1, 1), ("n", -2, 2), ("k", -1, 3), ("A", None, 4), ("lda", 3, 5),
+    ("C", None, 6), ("ldc", 5, 7), ("S", None, 8), ("lds", 2, 9)])
+def test_batch_names_entry_and_argument(field, value, argpos):
+    """Entry 2 (0-based) invalid -> -(1000*3 + argpos); nothing is launched."""
+    base = 0x10000000
+    probs = [_problem(8, 10, 4, base + i * 0x100000) for i in range(4)]
+    p = probs[2]
+    setattr(p, field, value)
+    probs[2] = p
+    assert _create(probs) == -(1000 * 3 + argpos)
+
+
+def test_batch_detects_overlapping_matrices():
+    base = 0x10000000
+    probs = [_problem(8, 10, 4, base), _problem(8, 10, 4, base + 0x100000),
+             _problem(8, 10, 4, base + 8 * 8 * 9)]  # starts inside entry 0's last column
+    assert _create(probs) == -(1000 * 3 + 4)
+
+
+def test_batch_null_handles_are_rejected():
+    lib = rs._lib._load()
+    assert lib.rotseq_batch_execute(None, None) == -1
+    assert lib.rotseq_batch_tune(None, None, 3) == -1
+    assert lib.rotseq_batch_info_get(None, None) == -1
+    assert lib.rotseq_batch_destroy(None) == 0
