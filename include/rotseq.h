@@ -46,7 +46,12 @@ extern "C" {
 #define ROTSEQ_E_NOMEM        2  /* device workspace could not be allocated     */
 #define ROTSEQ_E_WORKSPACE    3  /* caller workspace too small or misaligned    */
 #define ROTSEQ_E_UNSUPPORTED  4  /* option combination not supported           */
-#define ROTSEQ_E_TIMEOUT      5  /* a device-side wait exceeded its spin limit  */
+#define ROTSEQ_E_TIMEOUT      5  /* a device-side wait exceeded its spin limit,
+                                      or a server wait ran out of time           */
+#define ROTSEQ_E_BUDGET       6  /* a matrix alone exceeds the server's budget  */
+#define ROTSEQ_E_INVAL        7  /* unknown matrix id or ticket                 */
+#define ROTSEQ_E_CLOSED       8  /* the matrix was closed                       */
+#define ROTSEQ_E_FAILED       9  /* an earlier sweep of this matrix failed      */
 
 /* Arithmetic used for one rotation (options.arith). */
 #define ROTSEQ_ARITH_AUTO   0  /* library choice (currently ROTSEQ_ARITH_LIFT) */
@@ -266,6 +271,85 @@ int rotseq_batch_execute(rotseq_batch *batch, hipStream_t stream);
 int rotseq_batch_tune(rotseq_batch *batch, hipStream_t stream, int32_t reps);
 int rotseq_batch_info_get(const rotseq_batch *batch, rotseq_batch_info *info);
 int rotseq_batch_destroy(rotseq_batch *batch);
+
+/*
+ * Serving: resident matrices, each swept many times.
+ *
+ * A server keeps matrices resident in device memory (the paper keeps A
+ * packed across repeated applications, Section 4; the setting is repeated
+ * sweeps over the same matrix as in QR-type iterations, Section 5).  Clients
+ * open a matrix (its host data is copied at the call), submit sweeps (k
+ * sequences each; C and S are host arrays copied at the call, so the caller
+ * may reuse them at once), wait for tickets, read the matrix back and close
+ * it.  Sweeps of one matrix run in submission order; sweeps of different
+ * matrices are batched together (one preparation launch per stage and one
+ * sweep launch per batch, the batch path above) by a worker thread, with
+ * the host-to-device copies of the next batch overlapping the current one.
+ *
+ * Admission: an opened matrix stays pending until its bytes (8*lda*n) fit
+ * in the budget next to the resident ones; opens are admitted in order.
+ * FP64 only.  All calls are thread-safe.  Host pointers are read during the
+ * call only (open, submit) or written during the call (read).
+ */
+typedef struct rotseq_server rotseq_server;
+typedef int64_t rotseq_matrix_id;
+typedef int64_t rotseq_ticket;
+
+typedef struct rotseq_server_config {
+    uint64_t hbm_budget_bytes; /* resident matrices; 0 = 64 GiB              */
+    int32_t max_batch;         /* sweeps per launch; 0 = 512                 */
+    int32_t reserved[5];
+} rotseq_server_config;
+
+typedef struct rotseq_sweep_info {
+    int32_t status;            /* 0, or the ROTSEQ_E_* code of the failure   */
+    int32_t reserved;
+    double submit_us;          /* host clock, microseconds since create      */
+    double start_us;           /* its batch was launched                     */
+    double end_us;             /* its batch was seen complete                */
+} rotseq_sweep_info;
+
+typedef struct rotseq_server_stats {
+    int64_t sweeps_done;
+    int64_t sweeps_failed;
+    int64_t batches;
+    int64_t matrices_resident;
+    int64_t matrices_pending;
+    uint64_t resident_bytes;
+    uint64_t peak_resident_bytes;
+    double flops;              /* 6 m (n-1) k over completed sweeps          */
+    double busy_s;             /* first submit to last completion            */
+    double gflops;             /* flops / busy_s / 1e9                       */
+    double p50_us, p99_us;     /* sweep latency (submit to completion)       */
+    double mean_batch;         /* sweeps per launch                          */
+} rotseq_server_stats;
+
+/* Creates a server on the current device (its worker thread starts here).
+ * cfg NULL = defaults.  Returns 0, -1 (bad cfg) or -2 (out NULL), or an
+ * ROTSEQ_E_* code. */
+int rotseq_server_create(const rotseq_server_config *cfg, rotseq_server **out);
+/* Opens an m x n matrix (column-major host data, lda >= max(1,m)); returns
+ * at once with its id, admission may come later.  -i for a bad argument i,
+ * ROTSEQ_E_BUDGET if 8*max(1,m)*n exceeds the whole budget. */
+int rotseq_server_open(rotseq_server *srv, int64_t m, int64_t n, const double *A_host,
+                       int64_t lda, rotseq_matrix_id *id);
+/* Appends a sweep of k sequences (C, S host, (n-1) x k, column-major with
+ * ldc, lds >= max(1,n-1)) to matrix `id`; returns its ticket. */
+int rotseq_server_submit(rotseq_server *srv, rotseq_matrix_id id, int64_t k, const double *C_host,
+                         int64_t ldc, const double *S_host, int64_t lds, rotseq_ticket *ticket);
+/* Waits up to timeout_us (< 0: forever) for a ticket; fills `info` (may be
+ * NULL).  Returns the sweep's status, or ROTSEQ_E_TIMEOUT / ROTSEQ_E_INVAL. */
+int rotseq_server_wait(rotseq_server *srv, rotseq_ticket ticket, int64_t timeout_us,
+                       rotseq_sweep_info *info);
+/* Waits for every sweep submitted to `id` before this call, then copies the
+ * matrix to A_host (lda >= max(1,m)).  Blocks. */
+int rotseq_server_read(rotseq_server *srv, rotseq_matrix_id id, double *A_host, int64_t lda);
+/* Closes `id`: its queued sweeps still run, then its device memory is freed.
+ * Later submits and reads of `id` return ROTSEQ_E_CLOSED. */
+int rotseq_server_close(rotseq_server *srv, rotseq_matrix_id id);
+int rotseq_server_stats_get(rotseq_server *srv, rotseq_server_stats *stats);
+/* Runs everything queued, stops the worker and frees all device memory. */
+int rotseq_server_destroy(rotseq_server *srv);
 
 /* Static description of a return code. */
 const char *rotseq_strerror(int code);

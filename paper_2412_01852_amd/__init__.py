@@ -10,5 +10,5 @@ from ._lib import (  # noqa: F401
     KERNEL_AUTO, KERNEL_MULTIPASS, KERNEL_CHAIN,
     rotseq, check_args, workspace_bytes, strerror, version, library_path,
     device_colmajor, host_colmajor, profile_enable, profile_read, device_status,
-    Problem, BatchInfo, Batch, batched,
+    Problem, BatchInfo, Batch, batched, Server, ServerConfig, ServerStats, SweepInfo,
 )

@@ -51,6 +51,27 @@ class BatchInfo(ctypes.Structure):
                 ("bytes", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class SweepInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double),
+                ("end_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int64), ("sweeps_failed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("matrices_resident", ctypes.c_int64),
+                ("matrices_pending", ctypes.c_int64), ("resident_bytes", ctypes.c_uint64),
+                ("peak_resident_bytes", ctypes.c_uint64), ("flops", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("gflops", ctypes.c_double),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_batch", ctypes.c_double)]
+
+
 def profile_enable(on=True):
     _load().rotseq_profile_enable(1 if on else 0)
 
@@ -116,6 +137,21 @@ def _load():
     lib.rotseq_batch_info_get.restype = i32
     lib.rotseq_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     lib.rotseq_batch_destroy.restype, lib.rotseq_batch_destroy.argtypes = i32, [vp]
+    pv = ctypes.POINTER(ctypes.c_void_p)
+    lib.rotseq_server_create.restype = i32
+    lib.rotseq_server_create.argtypes = [ctypes.POINTER(ServerConfig), pv]
+    lib.rotseq_server_open.restype = i32
+    lib.rotseq_server_open.argtypes = [vp, i64, i64, vp, i64, ctypes.POINTER(i64)]
+    lib.rotseq_server_submit.restype = i32
+    lib.rotseq_server_submit.argtypes = [vp, i64, i64, vp, i64, vp, i64, ctypes.POINTER(i64)]
+    lib.rotseq_server_wait.restype = i32
+    lib.rotseq_server_wait.argtypes = [vp, i64, i64, ctypes.POINTER(SweepInfo)]
+    lib.rotseq_server_read.restype = i32
+    lib.rotseq_server_read.argtypes = [vp, i64, vp, i64]
+    lib.rotseq_server_close.restype, lib.rotseq_server_close.argtypes = i32, [vp, i64]
+    lib.rotseq_server_stats_get.restype = i32
+    lib.rotseq_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.rotseq_server_destroy.restype, lib.rotseq_server_destroy.argtypes = i32, [vp]
     _lib = lib
     return lib
 
@@ -309,3 +345,85 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _host_f64(a, name):
+    """A host float64 column-major array (a copy if needed) and its ld."""
+    import numpy as np
+    a = np.asarray(a)
+    if a.ndim != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if a.dtype != np.float64 or not (a.flags.f_contiguous or a.shape[1] <= 1):
+        a = np.asfortranarray(a, dtype=np.float64)
+    ld = a.strides[1] // 8 if a.shape[1] > 1 else max(1, a.shape[0])
+    return a, max(1, ld)
+
+
+class Server:
+    """rotseq_server_*: resident FP64 matrices, sweeps batched by a worker."""
+
+    def __init__(self, budget_bytes=0, max_batch=0):
+        cfg = ServerConfig(int(budget_bytes), int(max_batch))
+        self._h = ctypes.c_void_p()
+        rc = _load().rotseq_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
+        if rc != 0:
+            raise RotseqError(rc, "server_create")
+
+    def open(self, A):
+        a, ld = _host_f64(A, "A")
+        mid = ctypes.c_int64()
+        rc = _load().rotseq_server_open(self._h, a.shape[0], a.shape[1], a.ctypes.data if a.size else None,
+                                        ld, ctypes.byref(mid))
+        if rc != 0:
+            raise RotseqError(rc, "server_open")
+        return mid.value
+
+    def submit(self, mid, C, S):
+        c, ldc = _host_f64(C, "C")
+        s_, lds = _host_f64(S, "S")
+        t = ctypes.c_int64()
+        rc = _load().rotseq_server_submit(self._h, mid, c.shape[1], c.ctypes.data if c.size else None,
+                                          ldc, s_.ctypes.data if s_.size else None, lds,
+                                          ctypes.byref(t))
+        if rc != 0:
+            raise RotseqError(rc, "server_submit")
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        """Returns (status, info dict)."""
+        info = SweepInfo()
+        rc = _load().rotseq_server_wait(self._h, ticket, int(timeout_us), ctypes.byref(info))
+        return rc, {f: getattr(info, f) for f, _ in SweepInfo._fields_ if f != "reserved"}
+
+    def read(self, mid, m, n):
+        import numpy as np
+        out = np.zeros((m, n), dtype=np.float64, order="F")
+        rc = _load().rotseq_server_read(self._h, mid, out.ctypes.data if out.size else None, max(1, m))
+        if rc != 0:
+            raise RotseqError(rc, "server_read")
+        return out
+
+    def close(self, mid):
+        rc = _load().rotseq_server_close(self._h, mid)
+        if rc != 0:
+            raise RotseqError(rc, "server_close")
+
+    def stats(self):
+        st = ServerStats()
+        rc = _load().rotseq_server_stats_get(self._h, ctypes.byref(st))
+        if rc != 0:
+            raise RotseqError(rc, "server_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def destroy(self):
+        if self._h:
+            rc = _load().rotseq_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            if rc != 0:
+                raise RotseqError(rc, "server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()

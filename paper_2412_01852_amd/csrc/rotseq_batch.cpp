@@ -16,11 +16,88 @@ namespace rotseq {
 
 bool resolve_opts(const rotseq_opts *opts, int &arith, int &band, int &kernel);
 
+size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
+                    std::vector<BatchItem> &items, BatchLaunch &L)
+{
+    constexpr int kUnroll = 16;  // step unroll of the chain kernel
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    items.clear();
+    size_t off = a256((size_t)count * sizeof(BatchItem));
+    int64_t o_neg = 0, o_par = 0, o_sign = 0, o_coef = 0, o_flags = 0;
+    for (int i = 0; i < count; ++i) {
+        const BatchEntry &e = entries[i];
+        BatchItem it{};
+        it.A = e.A;
+        it.C = e.C;
+        it.S = e.S;
+        it.lda = e.lda;
+        it.ldc = e.ldc;
+        it.lds = e.lds;
+        it.m = e.m;
+        it.n = e.n;
+        it.k = e.k;
+        it.npass = (int)((e.k + band - 1) / band);
+        it.steps = (int)(((e.n + band - 1 + kUnroll - 1) / kUnroll) * kUnroll);
+        it.tiles = (int)((e.m + 63) / 64);
+        it.pad = kChainCoefPad;
+        const int64_t n1 = e.n - 1;
+        it.coef = (void *)off;
+        off = a256(off + (size_t)it.npass * (it.steps + it.pad) * band * 2 * esize);
+        it.negmask = (uint64_t *)off;
+        off = a256(off + (size_t)it.npass * n1 * sizeof(uint64_t));
+        it.parity = (uint8_t *)off;
+        off = a256(off + (size_t)(it.npass + 1) * n1);
+        it.sign = (void *)off;
+        off = a256(off + (size_t)e.n * esize);
+        it.flags = (int *)off;
+        off = a256(off + (size_t)it.tiles * it.npass * sizeof(int));
+        it.off_negmask = o_neg;
+        it.off_parity = o_par;
+        it.off_sign = o_sign;
+        it.off_coef = o_coef;
+        it.off_flags = o_flags;
+        o_neg += (int64_t)it.npass * n1;
+        o_par += n1;
+        o_sign += e.n;
+        o_coef += (int64_t)it.npass * (it.steps + it.pad) * band;
+        o_flags += (int64_t)it.tiles * it.npass;
+        items.push_back(it);
+    }
+    L.count = count;
+    L.band = band;
+    L.esize = esize;
+    L.total_negmask = o_neg;
+    L.total_parity = o_par;
+    L.total_sign = o_sign;
+    L.total_coef = o_coef;
+    L.total_flags = o_flags;
+    return off;
+}
+
+void batch_rebase(std::vector<BatchItem> &items, uintptr_t base)
+{
+    for (BatchItem &it : items) {
+        it.coef = (void *)(base + (uintptr_t)it.coef);
+        it.negmask = (uint64_t *)(base + (uintptr_t)it.negmask);
+        it.parity = (uint8_t *)(base + (uintptr_t)it.parity);
+        it.sign = (void *)(base + (uintptr_t)it.sign);
+        it.flags = (int *)(base + (uintptr_t)it.flags);
+    }
+}
+
+int64_t batch_assign_workgroups(std::vector<BatchItem> &items, int waves)
+{
+    int64_t wg = 0;
+    for (BatchItem &it : items) {
+        it.off_wg = wg;
+        const int64_t units = (int64_t)it.tiles * it.npass;
+        wg += (units + waves - 1) / waves;
+    }
+    return wg;
+}
+
 namespace {
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-constexpr int kBatchUnroll = 16;      // step unroll of the chain kernel
 constexpr int kDefaultWaves = 8;      // waves per workgroup before tuning
 constexpr int kTuneWaves[] = {2, 4, 8, 16};
 
@@ -57,18 +134,6 @@ struct rotseq_batch {
 namespace rotseq {
 namespace {
 
-// Workgroup ranges for `waves` waves per workgroup; returns the total.
-int64_t assign_workgroups(std::vector<BatchItem> &items, int waves)
-{
-    int64_t wg = 0;
-    for (BatchItem &it : items) {
-        it.off_wg = wg;
-        const int64_t units = (int64_t)it.tiles * it.npass;
-        wg += (units + waves - 1) / waves;
-    }
-    return wg;
-}
-
 int set_waves(rotseq_batch *b, int waves)
 {
     const size_t lds = chain_lds_bytes(b->L.band, waves, b->L.esize);
@@ -78,7 +143,7 @@ int set_waves(rotseq_batch *b, int waves)
     if (chain_occupancy(b->L.band, b->L.arith, b->L.esize, waves, lds, &occ, true) != hipSuccess ||
         occ < 1)
         return ROTSEQ_E_UNSUPPORTED;
-    const int64_t nwg = assign_workgroups(b->items, waves);
+    const int64_t nwg = batch_assign_workgroups(b->items, waves);
     if (nwg > (int64_t)INT32_MAX)
         return ROTSEQ_E_UNSUPPORTED;
     if (hipMemcpy(b->dmem, b->items.data(), b->items.size() * sizeof(BatchItem),
@@ -149,82 +214,34 @@ int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_
             return in[x].k > in[y].k;
         return x < y;
     });
-    size_t off = align256(work.size() * sizeof(BatchItem));
-    int64_t o_neg = 0, o_par = 0, o_sign = 0, o_coef = 0, o_flags = 0;
     for (int i : work) {
-        const Entry &e = in[i];
-        if (e.n > INT32_MAX - 64 || e.m > (int64_t)INT32_MAX * 64) {
+        if (in[i].n > INT32_MAX - 64 || in[i].m > (int64_t)INT32_MAX * 64) {
             delete b;
             return ROTSEQ_E_UNSUPPORTED;
         }
-        BatchItem it{};
-        it.A = e.A;
-        it.C = e.C;
-        it.S = e.S;
-        it.lda = e.lda;
-        it.ldc = e.ldc;
-        it.lds = e.lds;
-        it.m = e.m;
-        it.n = e.n;
-        it.k = e.k;
-        it.npass = (int)((e.k + band - 1) / band);
-        it.steps = (int)(((e.n + band - 1 + kBatchUnroll - 1) / kBatchUnroll) * kBatchUnroll);
-        it.tiles = (int)((e.m + 63) / 64);
-        it.pad = kChainCoefPad;
+    }
+    std::vector<BatchEntry> ordered;
+    for (int i : work) {
+        const Entry &e = in[i];
+        ordered.push_back(BatchEntry{e.A, e.C, e.S, e.m, e.n, e.k, e.lda, e.ldc, e.lds});
         const int64_t n1 = e.n - 1;
-        // Device addresses are filled in once the allocation exists; here
-        // they are offsets into it.
-        it.coef = (void *)off;
-        off = align256(off + (size_t)it.npass * (it.steps + it.pad) * band * 2 * esize);
-        it.negmask = (uint64_t *)off;
-        off = align256(off + (size_t)it.npass * n1 * sizeof(uint64_t));
-        it.parity = (uint8_t *)off;
-        off = align256(off + (size_t)(it.npass + 1) * n1);
-        it.sign = (void *)off;
-        off = align256(off + (size_t)e.n * esize);
-        it.flags = (int *)off;
-        off = align256(off + (size_t)it.tiles * it.npass * sizeof(int));
-        it.off_negmask = o_neg;
-        it.off_parity = o_par;
-        it.off_sign = o_sign;
-        it.off_coef = o_coef;
-        it.off_flags = o_flags;
-        o_neg += (int64_t)it.npass * n1;
-        o_par += n1;
-        o_sign += e.n;
-        o_coef += (int64_t)it.npass * (it.steps + it.pad) * band;
-        o_flags += (int64_t)it.tiles * it.npass;
-        b->items.push_back(it);
-        b->waves_total += (int64_t)it.tiles * it.npass;
         b->flops += 6.0 * (double)e.m * (double)n1 * (double)e.k;
         b->bytes += (double)esize * (2.0 * (double)e.m * (double)e.n + 2.0 * (double)n1 * (double)e.k);
     }
+    const size_t off = batch_layout(ordered.data(), (int)ordered.size(), band, esize, b->items, b->L);
+    for (const BatchItem &it : b->items)
+        b->waves_total += (int64_t)it.tiles * it.npass;
     b->dbytes = off;
     if (hipMalloc(&b->dmem, b->dbytes) != hipSuccess) {
         (void)hipGetLastError();
         delete b;
         return ROTSEQ_E_NOMEM;
     }
-    const uintptr_t base = (uintptr_t)b->dmem;
-    for (BatchItem &it : b->items) {
-        it.coef = (void *)(base + (uintptr_t)it.coef);
-        it.negmask = (uint64_t *)(base + (uintptr_t)it.negmask);
-        it.parity = (uint8_t *)(base + (uintptr_t)it.parity);
-        it.sign = (void *)(base + (uintptr_t)it.sign);
-        it.flags = (int *)(base + (uintptr_t)it.flags);
-    }
+    batch_rebase(b->items, (uintptr_t)b->dmem);
     BatchLaunch &L = b->L;
-    L.count = (int)b->items.size();
-    L.esize = esize;
     L.arith = arith;
-    L.band = band;
     L.publish = 1;
     L.spin_limit = 1 << 22;
-    L.total_negmask = o_neg;
-    L.total_parity = o_par;
-    L.total_sign = o_sign;
-    L.total_coef = o_coef;
-    L.total_flags = o_flags;
     L.items = (const BatchItem *)b->dmem;
     L.status = status;
     int waves = opts && opts->waves > 0 ? opts->waves : kDefaultWaves;

@@ -471,7 +471,11 @@ const char *rotseq_strerror(int code)
     case ROTSEQ_E_NOMEM: return "device workspace allocation failed";
     case ROTSEQ_E_WORKSPACE: return "caller workspace too small or not 256-byte aligned";
     case ROTSEQ_E_UNSUPPORTED: return "unsupported option combination";
-    case ROTSEQ_E_TIMEOUT: return "device-side wait exceeded its spin limit";
+    case ROTSEQ_E_TIMEOUT: return "wait timed out (device-side spin limit or server wait)";
+    case ROTSEQ_E_BUDGET: return "matrix exceeds the server's device memory budget";
+    case ROTSEQ_E_INVAL: return "unknown matrix id or ticket";
+    case ROTSEQ_E_CLOSED: return "matrix was closed";
+    case ROTSEQ_E_FAILED: return "an earlier sweep of this matrix failed";
     default: return "unknown error code";
     }
 }

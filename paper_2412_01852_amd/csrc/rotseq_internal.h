@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace rotseq {
 
 // Per-rotation arithmetic (values of rotseq_opts.arith after resolving AUTO).
@@ -70,6 +72,23 @@ struct BatchLaunch {
     const BatchItem *items;  // device copy, `count` entries
     int *status;
 };
+
+// One problem of a batch before layout (all fields as in rotseq_d).
+struct BatchEntry {
+    void *A;
+    const void *C, *S;
+    int64_t m, n, k, lda, ldc, lds;
+};
+// Lays out a batch in the given order: fills `items` and the totals of `L`
+// (count, band, esize, total_*); every device pointer of an item is an
+// offset from the start of one device block whose first bytes hold the item
+// table.  Returns the block's size.  Host-only.
+size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
+                    std::vector<BatchItem> &items, BatchLaunch &L);
+// Turns the offsets of batch_layout into addresses inside the block at `base`.
+void batch_rebase(std::vector<BatchItem> &items, uintptr_t base);
+// Workgroup ranges for `waves` waves per workgroup; returns their total.
+int64_t batch_assign_workgroups(std::vector<BatchItem> &items, int waves);
 
 hipError_t launch_prep_batch(const BatchLaunch &b, hipStream_t stream);
 // Host helpers of rotseq_host.cpp shared with the batch runtime.

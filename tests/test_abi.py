@@ -128,3 +128,24 @@ def test_batch_null_handles_are_rejected():
     assert lib.rotseq_batch_tune(None, None, 3) == -1
     assert lib.rotseq_batch_info_get(None, None) == -1
     assert lib.rotseq_batch_destroy(None) == 0
+
+
+def test_server_argument_checks_without_device():
+    lib = rs._lib._load()
+    assert lib.rotseq_server_create(None, None) == -2
+    cfg = rs.ServerConfig(0, -1)
+    h = ctypes.c_void_p()
+    assert lib.rotseq_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    mid = ctypes.c_int64()
+    assert lib.rotseq_server_open(None, 4, 4, None, 4, ctypes.byref(mid)) == -1
+    assert lib.rotseq_server_submit(None, 1, 4, None, 3, None, 3, ctypes.byref(mid)) == -1
+    assert lib.rotseq_server_wait(None, 1, 0, None) == -1
+    assert lib.rotseq_server_read(None, 1, None, 1) == -1
+    assert lib.rotseq_server_close(None, 1) == -1
+    assert lib.rotseq_server_stats_get(None, None) == -1
+    assert lib.rotseq_server_destroy(None) == 0
+
+
+def test_new_error_codes_have_descriptions():
+    for code in range(6, 10):
+        assert rs.strerror(code) != rs.strerror(999)
