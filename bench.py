@@ -38,6 +38,8 @@ WORKLOADS = {
        for k in (1, 8, 32, 128)},
 }
 BATCHED = {"batched-f64-512": dict(count=512, seed=4, dtype="f64")}
+SERVED = {"served-f64": dict(seed=5, n_lo=128, n_hi=4096, sweeps=20, ks=(16, 32, 64, 128),
+                             budget=64 << 30, load=0.7)}
 DEFAULT = "plain-f64-10240-k192"
 
 
@@ -189,12 +191,137 @@ def bench_batched(args):
     return 0
 
 
+def bench_served(args):
+    """Resident matrices under Poisson arrivals (the serving path).
+
+    Each request opens an n x n matrix (n log-uniform in [128, 4096]), runs
+    its sweeps one after another (each submitted when the previous one is
+    done, fresh angles every sweep, k fixed per request) and closes it.  A
+    closed-loop calibration (a burst of requests at once) measures the
+    saturated request rate; the open-loop run then offers `load` times that
+    rate.  Matrices are n x n windows of one N(0,1) pool and every sweep's
+    cosines/sines come from a different window of one pool of uniform angles,
+    so the host generates data once instead of per request.  Reports GFLOP/s
+    over the open-loop run, sweeps/s and the p50/p99 latency of sweeps
+    (submit to completion) and requests (arrival to completion).
+    """
+    import queue
+    import threading
+    import numpy as np
+    import paper_2412_01852_amd as rs
+    from paper_2412_01852_amd.inputs import served_requests
+
+    wl = SERVED[args.workload]
+    rng = np.random.Generator(np.random.PCG64(wl["seed"] + 77))
+    a_pool = np.asfortranarray(rng.standard_normal((wl["n_hi"], wl["n_hi"])))
+    theta = rng.uniform(0.0, 2.0 * np.pi, 1 << 23)
+    c_pool, s_pool = np.cos(theta), np.sin(theta)
+    span = (wl["n_hi"] - 1) * max(wl["ks"])
+
+    def run(srv, reqs, arrivals, workers=64):
+        lat_req = [0.0] * len(reqs)
+        errors = []
+        todo = queue.Queue()
+        for i in range(len(reqs)):
+            todo.put(i)
+        t_start = time.perf_counter()
+
+        def client():
+            while True:
+                try:
+                    i = todo.get_nowait()
+                except queue.Empty:
+                    return
+                r = reqs[i]
+                n, k = r["n"], r["k"]
+                delay = arrivals[i] - (time.perf_counter() - t_start)
+                if delay > 0:
+                    time.sleep(delay)
+                off = int(r["seed"].generate_state(1)[0]) % (len(theta) - span - 1)
+                try:
+                    mid = srv.open(a_pool[:n, :n])
+                    for sw in range(r["sweeps"]):
+                        o = (off + sw * 7919 * k) % (len(theta) - span - 1)
+                        C = c_pool[o:o + (n - 1) * k].reshape((n - 1, k), order="F")
+                        S = s_pool[o:o + (n - 1) * k].reshape((n - 1, k), order="F")
+                        rc, _ = srv.wait(srv.submit(mid, C, S))
+                        if rc != 0:
+                            errors.append(rc)
+                    srv.close(mid)
+                except Exception as e:  # reported below
+                    errors.append(repr(e))
+                lat_req[i] = time.perf_counter() - t_start - arrivals[i]
+
+        threads = [threading.Thread(target=client) for _ in range(workers)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        wall = time.perf_counter() - t_start
+        if errors:
+            raise RuntimeError(f"served run failed: {errors[:3]}")
+        return wall, lat_req
+
+    kw = dict(n_lo=wl["n_lo"], n_hi=wl["n_hi"], sweeps=wl["sweeps"], ks=wl["ks"])
+    cal = served_requests(128, seed=wl["seed"] + 1000, **kw)
+    with rs.Server(budget_bytes=wl["budget"]) as srv:
+        run(srv, cal[:16], [0.0] * 16)  # warm-up
+        wall_cal, _ = run(srv, cal, [0.0] * len(cal))
+    sat_rate = len(cal) / wall_cal  # requests per second when saturated
+    rate = wl["load"] * sat_rate
+    reqs = served_requests(args.requests, seed=wl["seed"], rate_per_s=rate, **kw)
+    arrivals = [r["arrival"] for r in reqs]
+    with rs.Server(budget_bytes=wl["budget"]) as srv:
+        wall, lat_req = run(srv, reqs, arrivals)
+        st = srv.stats()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+    flops = st["flops"]
+    sweeps = st["sweeps_done"]
+    out = {
+        "metric": METRIC,
+        "value": round(flops / wall / 1e9, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": sweeps,
+        "warmup": 16,
+        "ms_per_step": round(wall * 1e3 / max(sweeps, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Poisson arrivals; n log-uniform [128,4096], m=n; k per request in "
+                "{16,32,64,128}; A = windows of an N(0,1) pool, angles = windows of a U[0,2pi) "
+                "pool; seeded PCG64)",
+        "config": {"workload": args.workload, "requests": len(reqs),
+                   "sweeps_per_request": wl["sweeps"],
+                   "offered_requests_per_s": round(rate, 3), "load_vs_saturation": wl["load"],
+                   "budget_bytes": wl["budget"], "k_per": "request", "parallelism": "single GPU"},
+        "served": {
+            "wall_s": round(wall, 3),
+            "sweeps_per_s": round(sweeps / wall, 2),
+            "p50_sweep_us": round(st["p50_us"], 1),
+            "p99_sweep_us": round(st["p99_us"], 1),
+            "p50_request_s": round(float(np.percentile(lat_req, 50)), 4),
+            "p99_request_s": round(float(np.percentile(lat_req, 99)), 4),
+            "mean_batch": round(st["mean_batch"], 2),
+            "peak_resident_bytes": st["peak_resident_bytes"],
+            "saturated_requests_per_s": round(sat_rate, 3),
+            "server_busy_gflops": round(st["gflops"], 2),
+        },
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + sorted(BATCHED))
+    ap.add_argument("--workload", default=DEFAULT,
+                    choices=sorted(WORKLOADS) + sorted(BATCHED) + sorted(SERVED))
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="served workload: requests in the open-loop run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -205,6 +332,8 @@ def main():
 
     if args.workload in BATCHED:
         return bench_batched(args)
+    if args.workload in SERVED:
+        return bench_served(args)
 
     import numpy as np
     import torch

@@ -101,8 +101,10 @@ struct Matrix {
     int64_t id = 0, m = 0, n = 0;
     size_t bytes = 0;
     State state = State::kPending;
-    std::vector<double> init;  // host copy until admitted
+    double *init = nullptr;    // pinned host copy until its upload completed
+    size_t init_class = 0;
     double *dA = nullptr;      // lda = m (at least 1)
+    bool async_alloc = false;  // dA from hipMallocAsync
     std::deque<Task *> queue;
     bool inflight = false;
     bool failed = false;
@@ -150,6 +152,8 @@ struct rotseq_server {
     // worker-only state
     hipStream_t up = nullptr, comp = nullptr;
     hipEvent_t up_done = nullptr;
+    // Pinned admission copies whose upload may still be running.
+    std::vector<std::pair<hipEvent_t, rotseq::Matrix *>> uploading;
     rotseq::Arena arena[2];
     rotseq::PinnedPool pinned;
     size_t rr = 0;  // round-robin start over resident matrices
@@ -186,6 +190,8 @@ void finish(rotseq_server *s, Task *t, int status, double end_us)
 }
 
 // Admits pending matrices in open order while the budget allows (lock held).
+// Allocation and upload are ordered on the upload stream, which every later
+// batch, read and free waits for, so admission never blocks the worker.
 void admit(rotseq_server *s)
 {
     while (!s->admit.empty()) {
@@ -195,19 +201,50 @@ void admit(rotseq_server *s)
         s->admit.pop_front();
         double *d = nullptr;
         int rc = ROTSEQ_SUCCESS;
-        if (hipMalloc(&d, M->bytes) != hipSuccess) {
+        if (hipMallocAsync((void **)&d, M->bytes, s->up) == hipSuccess) {
+            M->async_alloc = true;
+        } else {
             (void)hipGetLastError();
-            rc = ROTSEQ_E_NOMEM;
-        } else if (hipMemcpy(d, M->init.data(), M->bytes, hipMemcpyHostToDevice) != hipSuccess) {
-            rc = ROTSEQ_E_HIP;
+            if (hipMalloc(&d, M->bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                d = nullptr;
+                rc = ROTSEQ_E_NOMEM;
+            }
         }
-        std::vector<double>().swap(M->init);
+        hipEvent_t ev = nullptr;
+        if (!rc && (hipMemcpyAsync(d, M->init, M->bytes, hipMemcpyHostToDevice, s->up) != hipSuccess ||
+                    hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+                    hipEventRecord(ev, s->up) != hipSuccess))
+            rc = ROTSEQ_E_HIP;
+        if (ev)
+            s->uploading.emplace_back(ev, M);
+        else {
+            (void)hipStreamSynchronize(s->up);
+            s->pinned.put(M->init, M->init_class);
+            M->init = nullptr;
+        }
         M->state = State::kResident;
         M->dA = d;
         s->resident += M->bytes;
         s->peak = std::max(s->peak, s->resident);
-        if (rc) {
+        if (rc)
             M->failed = true;
+    }
+}
+
+// Returns the pinned admission copies whose uploads have completed.
+void reap_uploads(rotseq_server *s)
+{
+    auto &v = s->uploading;
+    for (size_t i = 0; i < v.size();) {
+        if (hipEventQuery(v[i].first) == hipSuccess) {
+            s->pinned.put(v[i].second->init, v[i].second->init_class);
+            v[i].second->init = nullptr;
+            (void)hipEventDestroy(v[i].first);
+            v[i] = v.back();
+            v.pop_back();
+        } else {
+            ++i;
         }
     }
 }
@@ -225,16 +262,28 @@ void run_host_heads(rotseq_server *s, Matrix *M)
         if (t->op == Op::kSweep) {
             finish(s, t, ROTSEQ_E_FAILED, at);
         } else if (t->op == Op::kRead) {
+            // Nothing of this matrix is in flight on the compute stream; the
+            // upload stream orders the copy after its admission upload.
             const size_t row = (size_t)M->m * sizeof(double);
             int rc = M->failed ? ROTSEQ_E_FAILED : ROTSEQ_SUCCESS;
             if (!rc && M->m > 0 && M->n > 0 &&
-                hipMemcpy2D(t->host, (size_t)t->host_ld * sizeof(double), M->dA, row, row,
-                            (size_t)M->n, hipMemcpyDeviceToHost) != hipSuccess)
+                (hipMemcpy2DAsync(t->host, (size_t)t->host_ld * sizeof(double), M->dA, row, row,
+                                  (size_t)M->n, hipMemcpyDeviceToHost, s->up) != hipSuccess ||
+                 hipStreamSynchronize(s->up) != hipSuccess))
                 rc = ROTSEQ_E_HIP;
             finish(s, t, rc, at);
         } else {
-            if (M->dA)
-                (void)hipFree(M->dA);
+            // Freed behind everything already queued on both streams.
+            if (M->dA) {
+                (void)hipEventRecord(s->up_done, s->up);
+                (void)hipStreamWaitEvent(s->comp, s->up_done, 0);
+                if (M->async_alloc)
+                    (void)hipFreeAsync(M->dA, s->comp);
+                else {
+                    (void)hipStreamSynchronize(s->comp);
+                    (void)hipFree(M->dA);
+                }
+            }
             M->dA = nullptr;
             s->resident -= M->bytes;
             M->state = State::kFreed;
@@ -386,29 +435,39 @@ void worker_main(rotseq_server *s)
     (void)hipEventCreateWithFlags(&evs[1], hipEventDisableTiming);
     int slot = 0;
     for (;;) {
+        // Retire whatever has completed, without blocking.
+        while (!inflight.empty() && hipEventQuery(inflight.front().done) == hipSuccess) {
+            retire(s, inflight.front(), ROTSEQ_SUCCESS);
+            inflight.pop_front();
+        }
         InFlight f;
         bool quit = false;
         {
             std::unique_lock<std::mutex> lock(s->mu);
-            for (;;) {
-                admit(s);
+            reap_uploads(s);
+            admit(s);
+            if (inflight.size() < 2)
                 collect(s, f.tasks, f.mats);
-                if (!f.tasks.empty() || !inflight.empty())
-                    break;
-                // Stop once nothing runnable is left: resident queues are
-                // empty and no pending matrix fits.
-                bool busy = !s->admit.empty() && s->resident + s->admit.front()->bytes <= s->budget;
-                for (auto &kv : s->mats)
-                    busy = busy || (!kv.second->queue.empty() && kv.second->state == State::kResident);
-                if (s->stop && !busy) {
-                    quit = true;
-                    break;
+            if (f.tasks.empty()) {
+                if (inflight.empty()) {
+                    // Stop once nothing runnable is left: resident queues
+                    // are empty and no pending matrix fits.
+                    bool busy = !s->admit.empty() && s->resident + s->admit.front()->bytes <= s->budget;
+                    for (auto &kv : s->mats)
+                        busy = busy || (!kv.second->queue.empty() && kv.second->state == State::kResident);
+                    if (s->stop && !busy)
+                        quit = true;
+                    else
+                        s->cv_work.wait_for(lock, std::chrono::milliseconds(20));
+                } else if (inflight.size() < 2) {
+                    // A batch is running: wake for new work or poll again soon.
+                    s->cv_work.wait_for(lock, std::chrono::microseconds(20));
                 }
-                s->cv_work.wait_for(lock, std::chrono::milliseconds(50));
+            } else {
+                const double at = now_us(s);
+                for (Task *t : f.tasks)
+                    t->start_us = at;
             }
-            const double at = now_us(s);
-            for (Task *t : f.tasks)
-                t->start_us = at;
         }
         if (quit)
             break;
@@ -417,21 +476,23 @@ void worker_main(rotseq_server *s)
             f.done = evs[slot];
             slot ^= 1;
             const int rc = launch(s, f);
-            if (rc) {
+            if (rc)
                 retire(s, f, rc);
-            } else {
+            else
                 inflight.push_back(f);
-            }
-        }
-        // Keep at most two batches in flight; with nothing new, retire one.
-        if (inflight.size() >= 2 || (f.tasks.empty() && !inflight.empty())) {
-            retire(s, inflight.front(), ROTSEQ_SUCCESS);
+        } else if (inflight.size() >= 2) {
+            retire(s, inflight.front(), ROTSEQ_SUCCESS);  // blocks on the oldest
             inflight.pop_front();
         }
     }
     while (!inflight.empty()) {
         retire(s, inflight.front(), ROTSEQ_SUCCESS);
         inflight.pop_front();
+    }
+    (void)hipStreamSynchronize(s->up);
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        reap_uploads(s);
     }
     (void)hipEventDestroy(evs[0]);
     (void)hipEventDestroy(evs[1]);
@@ -494,10 +555,15 @@ int rotseq_server_open(rotseq_server *s, int64_t m, int64_t n, const double *A_h
         delete M;
         return ROTSEQ_E_BUDGET;
     }
-    M->init.assign(M->bytes / sizeof(double), 0.0);
+    M->init = (double *)s->pinned.get(M->bytes, M->init_class);
+    if (M->init == nullptr) {
+        delete M;
+        return ROTSEQ_E_NOMEM;
+    }
+    std::memset(M->init, 0, M->bytes);
     for (int64_t j = 0; j < n; ++j)
         if (m > 0)
-            std::memcpy(&M->init[(size_t)j * m], A_host + j * lda, (size_t)m * sizeof(double));
+            std::memcpy(M->init + (size_t)j * m, A_host + j * lda, (size_t)m * sizeof(double));
     {
         std::lock_guard<std::mutex> lock(s->mu);
         M->id = s->next_id++;
@@ -715,8 +781,14 @@ int rotseq_server_destroy(rotseq_server *s)
     int rc = hipDeviceSynchronize() == hipSuccess ? ROTSEQ_SUCCESS : ROTSEQ_E_HIP;
     for (auto &kv : s->mats) {
         Matrix *M = kv.second;
-        if (M->dA)
-            (void)hipFree(M->dA);
+        if (M->dA) {
+            if (M->async_alloc)
+                (void)hipFreeAsync(M->dA, s->comp);
+            else
+                (void)hipFree(M->dA);
+        }
+        if (M->init)
+            s->pinned.put(M->init, M->init_class);
         // Left only on matrices that were never admitted.  Sweeps are owned
         // by the ticket table; a read would still have a waiting caller,
         // which destroying the server under it does not allow.
@@ -736,6 +808,8 @@ int rotseq_server_destroy(rotseq_server *s)
         if (a.table)
             (void)hipHostFree(a.table);
     }
+    if (s->comp)
+        (void)hipStreamSynchronize(s->comp);
     if (s->up)
         (void)hipStreamDestroy(s->up);
     if (s->comp)
