@@ -43,13 +43,16 @@ SERVED = {"served-f64": dict(seed=5, n_lo=128, n_hi=4096, sweeps=20, ks=(16, 32,
 DEFAULT = "plain-f64-10240-k192"
 
 
+SWEEP_SOURCES = ("rotseq_chain.hip", "rotseq_device.h", "rotseq_internal.h")
+
+
 def kernel_source_hash():
+    """Hash of the sources the sweep kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2412_01852_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -320,6 +323,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(BATCHED) + sorted(SERVED))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (3 times), the "
+                         "reference for scaling HBM byte counters")
     ap.add_argument("--requests", type=int, default=2000,
                     help="served workload: requests in the open-loop run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -330,6 +336,16 @@ def main():
               "(rows shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         return 2
 
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 8
+        src = torch.randn(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
+        return 0
     if args.workload in BATCHED:
         return bench_batched(args)
     if args.workload in SERVED:
