@@ -319,8 +319,10 @@ def bench_served(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    # The GPU raises its clocks over the first few hundred milliseconds of
+    # sustained load; the untimed warm-up covers that.
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default=DEFAULT,
                     choices=sorted(WORKLOADS) + sorted(BATCHED) + sorted(SERVED))
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

@@ -72,7 +72,10 @@ struct ChainArgs {
     int *status;     // error word
 };
 
-constexpr int kCounters = 32;  // produced[0..15], consumed[16..31]
+// LDS counters: produced[16][64] then consumed[16][64] (one row per wave,
+// one slot per lane; every lane advances its own slot in the same
+// instruction, so any slot, read as slot 0, is the counter).
+constexpr int kCounterWords = 2 * 16 * 64;
 // A producer publishes column c only once its store has completed; it waits
 // for all but the newest kPublishLag stores, so it rarely waits at all.
 constexpr int kPublishLag = 16;
@@ -114,19 +117,18 @@ __device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, in
     return v;
 }
 
-// Adds 1 to an LDS counter from the wave's first lane only (`leader`):
-// one ds_add_u32 under a single-lane exec mask, no VALU work in the loop
-// (the library is built with the atomic optimizer off, which would otherwise
-// rewrite this into a wave-wide reduction).
-__device__ __forceinline__ void lds_inc(lds_counter *p, bool leader)
+// Adds 1 to a counter row: each lane to its own slot (`p` = row + lane), one
+// conflict-free ds_add_u32 of the whole wave.  No VALU instruction and no
+// change of the exec mask (a single-lane form costs a SALU exec write and a
+// pipeline bubble before the next VALU instruction, twice per step).
+__device__ __forceinline__ void lds_inc(lds_counter *p)
 {
-    if (leader)
-        __hip_atomic_fetch_add((__attribute__((address_space(3))) int *)p, 1, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add((__attribute__((address_space(3))) int *)p, 1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // The same LDS address, pinned in a VGPR once, so that lds_inc in the step
-// loop needs no VALU move to form its address operand.
+// loop needs no VALU instruction to form its address operand.
 __device__ __forceinline__ lds_counter *addr_in_vgpr(lds_counter *p)
 {
     uint32_t v = (uint32_t)(uintptr_t)p;
@@ -233,6 +235,7 @@ __device__ __forceinline__ void lift_step(double (&c)[9], double a, double b)
             : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3));
 }
 #undef ROTSEQ_COLS
+
 #undef ROTSEQ_ROT
 #undef ROTSEQ_FMAC
 
@@ -328,7 +331,6 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     typedef __attribute__((address_space(3))) T lds_T;
     const int n = a.n;
     const int lane = threadIdx.x & (kWave - 1);
-    const bool leader = lane == 0;
     const int64_t i0 = (int64_t)tile * kWave;
     const int64_t rows = a.m - i0 < kWave ? a.m - i0 : kWave;
     const uint32_t rowbytes = (uint32_t)(rows * (int64_t)sizeof(T));
@@ -340,10 +342,10 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
 
     __attribute__((address_space(3))) char *lds = (__attribute__((address_space(3))) char *)lds_generic;
     lds_counter *cnt = (lds_counter *)lds;
-    lds_T *rings = (lds_T *)(lds + kCounters * sizeof(int));
-    lds_counter *prod_in = cnt + (w - 1), *cons_in = cnt + 16 + (w - 1);
-    lds_counter *prod_out = cnt + w, *cons_out = cnt + 16 + w;
-    lds_counter *cons_in_v = addr_in_vgpr(cons_in), *prod_out_v = addr_in_vgpr(prod_out);
+    lds_T *rings = (lds_T *)(lds + kCounterWords * sizeof(int));
+    lds_counter *prod_in = cnt + (w - 1) * kWave, *cons_in = cnt + (16 + w - 1) * kWave;
+    lds_counter *prod_out = cnt + w * kWave, *cons_out = cnt + (16 + w) * kWave;
+    lds_counter *cons_in_v = addr_in_vgpr(cons_in + lane), *prod_out_v = addr_in_vgpr(prod_out + lane);
     lds_T *ring_in = rings + (w - 1) * RB * SLOT + lane;
     lds_T *ring_out = rings + w * RB * SLOT + lane;
     int *flag_in = a.flags + (int64_t)tile * a.nbands + (b - 1);
@@ -400,7 +402,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     opaque_i(lc);
     if constexpr (IN == kInLds) {
         compiler_fence();
-        *cons_in = lc;
+        *cons_in_v = lc;
         in_poll = *prod_in;
     } else if constexpr (IN == kInWait) {
         in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -441,6 +443,30 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     if constexpr (kSign)
         sg = sign[0];
     int blk = 0;
+    // Column t-K+1 (step uu of the block) has seen the whole band: to the
+    // next band's LDS ring, or to A (with its final sign in the last band).
+    auto emit = [&](int uu) {
+        T val = ring[(uu - K + 1 + U) % R];
+        if constexpr (OUT == kOutLds) {
+            ring_out[((uu - K + 1 + U) % RB) * SLOT] = val;
+            compiler_fence();
+            lds_inc(prod_out_v);
+        } else {
+            const int c = sc + (uu % G);
+            const bool valid = (unsigned)c < (unsigned)n;
+            if constexpr (kSign) {
+                val *= sg;
+                const int cn = c + 1;
+                sg = sign[(unsigned)cn < (unsigned)n ? cn : 0];
+            }
+            if constexpr (OUT == kOutPublish)
+                buf_store<kPolicyDevice>(val, make_rsrc(sp, valid ? rowbytes : 0u), voff);
+            else
+                buf_store(val, make_rsrc(sp, valid ? rowbytes : 0u), voff);
+            sp += ldab;
+            opaque(sp);
+        }
+    };
     // Drain the prologue's loads once: the compiler's wait-count analysis
     // merges the loop entry with the back edge, and a load still in flight
     // from the prologue would make it wait for nearly every load at the top
@@ -486,7 +512,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
             fetch(ring[(u + D + 1) % R], (u + D + 1) % RB);
             if constexpr (IN == kInLds) {
                 compiler_fence();
-                lds_inc(cons_in_v, leader);
+                lds_inc(cons_in_v);
             }
             select_const<SPL>(u % SPL, [&](auto jc) {
                 constexpr int OFF = decltype(jc)::value * K;
@@ -512,27 +538,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                     });
                 }
             });
-            // Column sc = t-K+1 has seen the whole band.
-            T val = ring[(u - K + 1 + U) % R];
-            if constexpr (OUT == kOutLds) {
-                ring_out[((u - K + 1 + U) % RB) * SLOT] = val;
-                compiler_fence();
-                lds_inc(prod_out_v, leader);
-            } else {
-                const int c = sc + (u % G);
-                const bool valid = (unsigned)c < (unsigned)n;
-                if constexpr (kSign) {
-                    val *= sg;
-                    const int cn = c + 1;
-                    sg = sign[(unsigned)cn < (unsigned)n ? cn : 0];
-                }
-                if constexpr (OUT == kOutPublish)
-                    buf_store<kPolicyDevice>(val, make_rsrc(sp, valid ? rowbytes : 0u), voff);
-                else
-                    buf_store(val, make_rsrc(sp, valid ? rowbytes : 0u), voff);
-                sp += ldab;
-                opaque(sp);
-            }
+            emit(u);
             if (u % G == G - 1) {
                 sc += G;
                 opaque_i(lc);
@@ -778,7 +784,7 @@ int chain_unroll(int band)
 size_t chain_lds_bytes(int band, int waves, int esize)
 {
     (void)band;
-    return kCounters * sizeof(int) + (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
+    return kCounterWords * sizeof(int) + (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
 }
 
 hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,

@@ -207,3 +207,22 @@ def test_repeated_calls_reuse_pool():
         got, ref, _ = run_full(pb, "f64")
         assert relerr(got, ref, pb.A) <= TOL["f64"]
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("band", [4, 8])
+@pytest.mark.parametrize("arith", ["lift", "fma"])
+def test_chain_bitwise_equals_multipass(band, arith):
+    """Both kernels apply, per element, the same FMAs in the same order (the
+    chain kernel's two-step interleave included), so they agree bitwise."""
+    import torch
+    say(f"chain vs multipass bitwise band={band} arith={arith}")
+    pb = make_problem(300, 700, 37, seed=5 + band)
+    outs = []
+    for kern in (rs.KERNEL_CHAIN, rs.KERNEL_MULTIPASS):
+        A = to_dev(pb.A, "f64")
+        rs.rotseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"),
+                  opts={"kernel": kern, "band": band, "arith": ARITHS[arith]})
+        torch.cuda.synchronize()
+        outs.append(A)
+    assert rs.device_status(reset=True) == 0
+    assert torch.equal(outs[0], outs[1])

@@ -43,8 +43,11 @@ def chain_asm(tmp_path_factory):
 
 
 def test_no_valu_write_before_dpp_read(chain_asm):
+    # Compiler output lines start with a tab; the lines of a multi-line
+    # inline asm block after its first do not, so take every line that
+    # starts with an instruction mnemonic.
     ins = [l.strip() for l in chain_asm.split("\n")
-           if l.startswith("\t") and not l.strip().startswith((";", "."))]
+           if re.match(r"\s*(v|s|ds|buffer|global|flat|scratch)_[a-z0-9_]+(\s|$)", l)]
     ndpp = 0
     bad = []
     for i, t in enumerate(ins):
