@@ -215,7 +215,7 @@ int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_
         return x < y;
     });
     for (int i : work) {
-        if (in[i].n > INT32_MAX - 64 || in[i].m > (int64_t)INT32_MAX * 64) {
+        if (in[i].n > ((int64_t)1 << 28) || in[i].m > (int64_t)INT32_MAX * 64) {
             delete b;
             return ROTSEQ_E_UNSUPPORTED;
         }

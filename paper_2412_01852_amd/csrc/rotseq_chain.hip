@@ -301,9 +301,7 @@ enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel 
 // output) may overwrite the slot of column c - RB once consumed > c - RB.
 // Both counters advance every step (an LDS atomic add after the slot access)
 // and are re-read asynchronously (an LDS load issued one step before the
-// group), so a wave only stalls when its neighbour really is behind; when it
-// must wait it waits for extra headroom (kInSlack columns, kOutSlack slots)
-// so the next wait is further away.
+// group), so a wave only stalls when its neighbour really is behind.
 //
 // Channel reads and writes are unconditional: columns outside [0, n)
 // travel as data too (zeros, or past n possibly an older finite column of
@@ -319,15 +317,18 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     constexpr int D = R - K - 1;
     constexpr int SLOT = kWave;  // elements per ring slot
     constexpr int G = 4;         // steps per flow-control group
-    // Counters move in steps of G, so a blocked consumer (waiting for
-    // produced >= lc + G + kInSlack) and a blocked producer (waiting for
-    // consumed >= sc + G - RB + kOutSlack) can never block each other as
-    // long as kInSlack + kOutSlack <= RB + 1 - 2G.
+    // A blocked consumer waits for produced >= lc + G + kInSlack, a blocked
+    // producer for consumed >= sc + G - RB + kOutSlack; the two can never
+    // block each other as long as kInSlack + kOutSlack <= RB + 1 - 2G.  No
+    // extra headroom is asked for: with counters current to the step, a
+    // wave that waits only for what its next group needs resumes soonest
+    // (measured faster than waiting for half the ring).
     constexpr int kSlack = RB + 1 - 2 * G;
-    constexpr int kInSlack = (kSlack + 1) / 2;
-    constexpr int kOutSlack = kSlack - kInSlack;
+    constexpr int kInSlack = 0;
+    constexpr int kOutSlack = 0;
     static_assert(U % G == 0, "groups must tile the unroll");
-    static_assert(kInSlack >= 0 && kOutSlack >= 0, "ring too small for the group size");
+    static_assert(kInSlack >= 0 && kOutSlack >= 0 && kInSlack + kOutSlack <= kSlack,
+                  "ring too small for the group size");
     typedef __attribute__((address_space(3))) T lds_T;
     const int n = a.n;
     const int lane = threadIdx.x & (kWave - 1);
@@ -439,9 +440,30 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         cf[i] = CL::load(crs, cvoff, i * SPL * kStepBytes);
     ConstScalars<T> sign = (ConstScalars<T>)a.sign;
     constexpr bool kSign = OUT == kOutFinal && ARITH == kLift;
+    // FP64: the final signs of a block's 16 output columns come in with one
+    // vector load per block (lane l of each row: column sc + l mod 16 of the
+    // block; 0 outside [0, n), where stores are dropped anyway), a block
+    // ahead, and each step broadcasts its column's sign with DPP.  Scalar
+    // loads in the step loop would force full LDS waits (scalar loads
+    // complete out of order), every step, in the wave that ends each chain.
+    constexpr bool kSignV = kSign && sizeof(T) == 8;
     T sg = T(1);
-    if constexpr (kSign)
+    if constexpr (kSign && !kSignV)
         sg = sign[0];
+    // The range check of a buffer access covers the vector offset only, so
+    // the column offset (negative, hence out of range, for the first block's
+    // leading lanes) lives in a VGPR.
+    __amdgpu_buffer_rsrc_t srs;
+    u32x2 sgn_cur, sgn_next;
+    int svoff = 0;  // byte offset of this lane's column in the next block
+    if constexpr (kSignV) {
+        srs = make_rsrc(a.sign, (uint32_t)((int64_t)n * (int64_t)sizeof(T)));
+        svoff = (-(K - 1) + (lane & 15)) * (int)sizeof(T);
+        sgn_cur = __builtin_amdgcn_raw_buffer_load_b64(srs, svoff, 0, 0);
+        svoff += U * (int)sizeof(T);
+        sgn_next = __builtin_amdgcn_raw_buffer_load_b64(srs, svoff, 0, 0);
+        svoff += U * (int)sizeof(T);
+    }
     int blk = 0;
     // Column t-K+1 (step uu of the block) has seen the whole band: to the
     // next band's LDS ring, or to A (with its final sign in the last band).
@@ -454,7 +476,11 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         } else {
             const int c = sc + (uu % G);
             const bool valid = (unsigned)c < (unsigned)n;
-            if constexpr (kSign) {
+            if constexpr (kSignV) {
+                select_const<U>(uu % U, [&](auto qc) {
+                    val *= bcast<decltype(qc)::value>(__builtin_bit_cast(double, sgn_cur));
+                });
+            } else if constexpr (kSign) {
                 val *= sg;
                 const int cn = c + 1;
                 sg = sign[(unsigned)cn < (unsigned)n ? cn : 0];
@@ -545,6 +571,11 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                 opaque_i(sc);
             }
             __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (kSignV) {
+            sgn_cur = sgn_next;
+            sgn_next = __builtin_amdgcn_raw_buffer_load_b64(srs, svoff, 0, 0);
+            svoff += U * (int)sizeof(T);
         }
         coff += U * kStepBytes;
         opaque_i(coff);

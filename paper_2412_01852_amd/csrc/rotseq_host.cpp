@@ -19,7 +19,12 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool make_plan(Plan &p, int req_kernel, int req_band)
 {
-    p.kernel = req_kernel == 0 ? kChain : req_kernel;
+    // The chain kernel addresses the n column signs with 32-bit byte
+    // offsets; past 2^28 columns the multipass kernel takes over.
+    constexpr int64_t kChainMaxN = (int64_t)1 << 28;
+    p.kernel = req_kernel == 0 ? (p.n <= kChainMaxN ? kChain : kMultipass) : req_kernel;
+    if (p.kernel == kChain && p.n > kChainMaxN)
+        return false;
     int band = req_band;
     if (p.kernel == kChain) {
         if (band == 0)
@@ -119,10 +124,8 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
     // rounds x (waves per SIMD in a round): `occ` workgroups fit on a CU at
     // once (registers and LDS), so ceil(nwg / (occ * CUs)) rounds run one
     // after another, and within a round the busiest SIMD holds
-    // ceil(W * wgs_per_cu / 4) waves.  Among equal costs, two or more
-    // workgroups per CU win (each SIMD then interleaves waves of independent
-    // chains, whose stalls do not coincide; measured 6% faster at 10240^2,
-    // k = 192), then fewer workgroups (fewer hand-offs through A).
+    // ceil(W * wgs_per_cu / 4) waves.  Ties go to fewer workgroups (fewer
+    // hand-offs through A).
     int waves = 0, per_cu = 1;
     size_t lds = 0;
     if (req_waves > 0) {
@@ -145,8 +148,7 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
             const int64_t in_round = std::min<int64_t>(nwg, slots);
             const int64_t wg_per_cu = (in_round + d.cus - 1) / d.cus;
             const int64_t simd_waves = (wv * wg_per_cu + 3) / 4;
-            const double cost = (double)rounds * (double)simd_waves + (wg_per_cu < 2 ? 0.5 : 0.0) +
-                                1e-6 * (double)nwg;
+            const double cost = (double)rounds * (double)simd_waves + 1e-6 * (double)nwg;
             if (cost < best) {
                 best = cost;
                 waves = wv;

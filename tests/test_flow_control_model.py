@@ -23,9 +23,8 @@ import random
 import pytest
 
 RB, G = 16, 4
-SLACK = RB + 1 - 2 * G
-IN_SLACK = (SLACK + 1) // 2
-OUT_SLACK = SLACK - IN_SLACK
+SLACK = RB + 1 - 2 * G   # the deadlock-free bound on IN_SLACK + OUT_SLACK
+IN_SLACK = OUT_SLACK = 0  # what the kernel asks for
 
 
 def simulate(n, k_lag, d_cons, in_slack, out_slack, seed, max_ticks=400000, per_step=True):
@@ -146,4 +145,12 @@ def test_bound_is_tight_for_per_step_protocol():
 
 def test_slack_bound():
     assert IN_SLACK + OUT_SLACK <= RB + 1 - 2 * G
-    assert IN_SLACK >= 1 and OUT_SLACK >= 1
+    assert IN_SLACK >= 0 and OUT_SLACK >= 0
+
+
+@pytest.mark.parametrize("per_step", [True, False])
+@pytest.mark.parametrize("seed", range(20))
+def test_protocol_finishes_at_the_bound(seed, per_step):
+    """Headroom exactly at the bound (5 + 4) is still deadlock-free."""
+    for k_lag, d_cons in [(6, 1), (8, 7), (4, 3)]:
+        assert simulate(300, k_lag, d_cons, 5, 4, seed, per_step=per_step)
