@@ -88,6 +88,12 @@ extern "C" {
  *           (sized so the workgroups match the CU count).
  *   publish CHAIN only: columns between progress updates across
  *           workgroups (rounded up to a power of 2); 0 = auto (32).
+ *   inverse nonzero: apply the inverse product instead,
+ *               A <- A * (G(0,0) ... G(n-2,k-1))^T
+ *                  = A * G(n-2,k-1)^T ... G(0,0)^T,
+ *           i.e. the rotations in reverse order (p and j descending) with
+ *           s negated; it undoes a forward call up to rounding.  In
+ *           exact mode it equals that loop bitwise.  Not for batches.
  */
 typedef struct rotseq_opts {
     int32_t arith;
@@ -95,7 +101,8 @@ typedef struct rotseq_opts {
     int32_t band;
     int32_t waves;
     int32_t publish;
-    int32_t reserved[3];
+    int32_t inverse;
+    int32_t reserved[2];
 } rotseq_opts;
 
 /*

@@ -27,7 +27,8 @@ class RotseqError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("arith", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("publish", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("publish", ctypes.c_int32), ("inverse", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Profile(ctypes.Structure):

@@ -344,6 +344,7 @@ bool plan_for(Plan &p, int esize, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.lda = lda;
     p.ldc = ldc;
     p.lds = lds;
+    p.cstep = 1;
     p.arith = arith;
     p.esize = esize;
     return make_plan(p, kernel, band);
@@ -363,6 +364,20 @@ int run(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C, int64_t 
         return ROTSEQ_E_UNSUPPORTED;
     if (n > INT32_MAX - 64 || p.steps <= 0)
         return ROTSEQ_E_UNSUPPORTED;
+    if (opts && opts->inverse) {
+        // The inverse applies, for p = k-1..0 and j = n-2..0, the rotation
+        // (c, -s) to columns (j, j+1).  On the column-reversed matrix
+        // A'(:, i) = A(:, n-1-i) that is the rotation (c, s) on columns
+        // (n-2-j, n-1-j) in the forward order of Algorithm 2, with
+        // C'(i, q) = C(n-2-i, k-1-q): a forward call on reversed views.
+        A += (n - 1) * lda;
+        p.lda = -lda;
+        C += (n - 2) + (k - 1) * ldc;
+        S += (n - 2) + (k - 1) * lds;
+        p.ldc = -ldc;
+        p.lds = -lds;
+        p.cstep = -1;
+    }
     if (configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (ws) {

@@ -29,7 +29,11 @@ constexpr int kChainCoefPad = 17;
 // multipass kernel, kChainCoefPad for the chain kernel): sweeps prefetch
 // records past their last step, which are identity padding.
 struct Plan {
+    // lda, ldc, lds may be negative and cstep is 1 or -1: the inverse call
+    // runs the forward sweep on a column-reversed view of A with C and S
+    // read backwards (see run() in rotseq_host.cpp).
     int64_t m, n, k, lda, ldc, lds;
+    int64_t cstep;  // step between C(j,p) and C(j+1,p) (and likewise S)
     int kernel;  // Kernel
     int band;    // sequences per band (K)
     int npass;   // number of bands

@@ -211,14 +211,14 @@ __device__ __forceinline__ uint64_t low_bits(int q) { return q >= 64 ? ~0ull : (
 
 // negmask[pass*(n-1) + j] bit q = [C(j, pass*K + q) < 0].
 template <typename T>
-__device__ __forceinline__ uint64_t negmask_elem(const T *__restrict__ C, int64_t ldc, int64_t n1,
-                                                 int64_t k, int K, int64_t idx)
+__device__ __forceinline__ uint64_t negmask_elem(const T *__restrict__ C, int64_t cj, int64_t ldc,
+                                                 int64_t n1, int64_t k, int K, int64_t idx)
 {
     const int64_t pass = idx / n1, j = idx - pass * n1;
     uint64_t mask = 0;
     for (int q = 0; q < K; ++q) {
         const int64_t p = pass * K + q;
-        if (p < k && C[j + p * ldc] < T(0))
+        if (p < k && C[j * cj + p * ldc] < T(0))
             mask |= 1ull << q;
     }
     return mask;
@@ -249,7 +249,7 @@ __device__ __forceinline__ T sign_elem(const uint8_t *__restrict__ total, int64_
 // or the identity where that rotation does not exist (t >= steps is always
 // identity padding).
 template <typename T>
-__device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_t ldc,
+__device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_t cj, int64_t ldc,
                                                  const T *__restrict__ S, int64_t lds, int64_t n1,
                                                  int64_t k, int K, int steps, int pad, int arith,
                                                  const uint64_t *__restrict__ negmask,
@@ -261,7 +261,7 @@ __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_
     const int64_t j = t - q, p = pass * K + q;
     CoefPair<T> out;
     if (j >= 0 && j < n1 && p < k) {
-        const T c = C[j + p * ldc], s = S[j + p * lds];
+        const T c = C[j * cj + p * ldc], s = S[j * cj + p * lds];
         if (arith == kLift) {
             const uint64_t *nm = negmask + pass * n1;
             const uint8_t *par = parity + pass * n1;
@@ -294,13 +294,13 @@ __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_
 }
 
 template <typename T>
-__global__ void prep_negmask(const T *__restrict__ C, int64_t ldc, int64_t n1, int64_t k, int K,
-                             int npass, uint64_t *__restrict__ negmask)
+__global__ void prep_negmask(const T *__restrict__ C, int64_t cj, int64_t ldc, int64_t n1, int64_t k,
+                             int K, int npass, uint64_t *__restrict__ negmask)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)npass * n1)
         return;
-    negmask[idx] = negmask_elem(C, ldc, n1, k, K, idx);
+    negmask[idx] = negmask_elem(C, cj, ldc, n1, k, K, idx);
 }
 
 __global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
@@ -322,7 +322,7 @@ __global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__res
 }
 
 template <typename T>
-__global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S,
+__global__ void prep_coef(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
                           int64_t lds, int64_t n1, int64_t k, int K, int steps, int pad, int npass,
                           int arith, const uint64_t *__restrict__ negmask,
                           const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
@@ -331,7 +331,7 @@ __global__ void prep_coef(const T *__restrict__ C, int64_t ldc, const T *__restr
     const int64_t total = (int64_t)npass * (steps + pad) * K;
     if (idx >= total)
         return;
-    coef[idx] = coef_elem(C, ldc, S, lds, n1, k, K, steps, pad, arith, negmask, parity, idx);
+    coef[idx] = coef_elem(C, cj, ldc, S, lds, n1, k, K, steps, pad, arith, negmask, parity, idx);
 }
 
 __global__ void prep_zero(int *__restrict__ p, int64_t count)
@@ -390,13 +390,13 @@ __global__ void prep_batch(const BatchItem *__restrict__ items, int count, int64
     const int64_t i = idx - stage_off<STAGE>(it);
     const int64_t n1 = it.n - 1;
     if constexpr (STAGE == kStageNegmask)
-        it.negmask[i] = negmask_elem((const T *)it.C, it.ldc, n1, it.k, K, i);
+        it.negmask[i] = negmask_elem((const T *)it.C, 1, it.ldc, n1, it.k, K, i);
     else if constexpr (STAGE == kStageParity)
         parity_elem(it.negmask, n1, it.npass, it.parity, i);
     else if constexpr (STAGE == kStageSign)
         ((T *)it.sign)[i] = sign_elem<T>(it.parity + (int64_t)it.npass * n1, it.n, i);
     else if constexpr (STAGE == kStageCoef)
-        ((CoefPair<T> *)it.coef)[i] = coef_elem((const T *)it.C, it.ldc, (const T *)it.S, it.lds, n1,
+        ((CoefPair<T> *)it.coef)[i] = coef_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1,
                                                 it.k, K, it.steps, it.pad, arith, it.negmask,
                                                 it.parity, i);
     else
@@ -415,8 +415,8 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
     CoefPair<T> *coef = (CoefPair<T> *)(ws + p.off_coef);
     constexpr int B = 256;
     if (p.arith == kLift) {
-        prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(C, p.ldc, n1, p.k, p.band,
-                                                                          p.npass, negmask);
+        prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(C, p.cstep, p.ldc, n1, p.k,
+                                                                          p.band, p.npass, negmask);
         prep_parity<<<blocks_for(n1, B), B, 0, st>>>(negmask, n1, p.npass, parity);
         prep_sign<T><<<blocks_for(p.n, B), B, 0, st>>>(parity + (int64_t)p.npass * n1, p.n, sign);
     }
@@ -425,8 +425,9 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
         const int64_t words = ((p.m + 63) / 64) * (int64_t)p.npass;
         prep_zero<<<blocks_for(words, B), B, 0, st>>>((int *)(ws + p.off_flags), words);
     }
-    prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.ldc, S, p.lds, n1, p.k, p.band, p.steps,
-                                                    p.pad, p.npass, p.arith, negmask, parity, coef);
+    prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band,
+                                                    p.steps, p.pad, p.npass, p.arith, negmask, parity,
+                                                    coef);
     return hipGetLastError();
 }
 

@@ -149,3 +149,10 @@ def test_server_argument_checks_without_device():
 def test_new_error_codes_have_descriptions():
     for code in range(6, 10):
         assert rs.strerror(code) != rs.strerror(999)
+
+
+def test_options_struct_layout():
+    """rotseq_opts is eight int32 fields: arith, kernel, band, waves, publish,
+    inverse, reserved[2]."""
+    assert ctypes.sizeof(rs.Options) == 32
+    assert rs.Options.inverse.offset == 20

@@ -226,3 +226,55 @@ def test_chain_bitwise_equals_multipass(band, arith):
         outs.append(A)
     assert rs.device_status(reset=True) == 0
     assert torch.equal(outs[0], outs[1])
+
+
+INVERSE = [(130, 17, 33, 2, 3, 1), (64, 64, 64, 0, 0, 0), (1, 2, 1, 0, 0, 0), (200, 2, 9, 1, 0, 0),
+           (3, 129, 128, 1, 1, 1), (257, 300, 20, 3, 0, 0)]
+
+
+@pytest.mark.parametrize("m,n,k,pa,pc,ps", INVERSE)
+@pytest.mark.parametrize("arith", ["exact", "lift"])
+@pytest.mark.parametrize("kernel", ["chain", "multipass"])
+def test_inverse_fp64(m, n, k, pa, pc, ps, arith, kernel):
+    """opts.inverse applies A <- A Q^T: against the oracle's inverse (bitwise
+    in exact mode) and as the undo of a forward call."""
+    import torch
+    say(f"inverse fp64 m={m} n={n} k={k} arith={arith} kernel={kernel}")
+    pb = make_problem(m, n, k, seed=3 * m + n + k,
+                      lda=max(1, m) + pa, ldc=max(1, n - 1) + pc, lds=max(1, n - 1) + ps)
+    kern = rs.KERNEL_CHAIN if kernel == "chain" else rs.KERNEL_MULTIPASS
+    A = to_dev(pb.A, "f64")
+    C, S = to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    pad_before = padding_bits(A)
+    rs.rotseq(A, C, S, opts={"arith": ARITHS[arith], "kernel": kern, "inverse": 1})
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
+    assert np.array_equal(pad_before, padding_bits(A))
+    got = rs.host_colmajor(A)
+    ref = oracle.colmajor(np.asarray(pb.A))
+    oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S), inverse=True)
+    ref = np.asarray(ref)
+    if arith == "exact":
+        assert np.array_equal(got, ref), "exact inverse must equal the oracle's inverse loop bitwise"
+    else:
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+    # forward then inverse recovers A
+    rs.rotseq(A, C, S, opts={"arith": ARITHS[arith], "kernel": kern})
+    torch.cuda.synchronize()
+    assert relerr(rs.host_colmajor(A), np.asarray(pb.A), pb.A) <= 2 * TOL["f64"]
+
+
+def test_inverse_target_sampled():
+    """Inverse at 10240^2, k = 192 in the bench's launch shape, sampled rows."""
+    import torch
+    say("inverse 10240^2 k=192 sampled rows")
+    pb = make_problem(10240, 10240, 192, seed=2)
+    A = to_dev(pb.A, "f64")
+    rs.rotseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"), opts={"inverse": 1})
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
+    rows = np.array([0, 1, 63, 64, 5000, 10238, 10239])
+    sub = oracle.colmajor(np.asarray(pb.A)[rows])
+    oracle.rotseq(sub, oracle.colmajor(pb.C), oracle.colmajor(pb.S), inverse=True)
+    got = rs.host_colmajor(A)[rows]
+    assert relerr(got, np.asarray(sub), np.asarray(pb.A)[rows]) <= TOL["f64"]
