@@ -30,7 +30,9 @@ def _load(path=None):
             _b.build()
         lib = ctypes.CDLL(_LIB_PATH)
     i64, dp = ctypes.c_int64, ctypes.c_void_p
-    for name in ("oracle_rotseq_d", "oracle_rotseq_inverse_d"):
+    for name in ("oracle_rotseq_d", "oracle_rotseq_inverse_d", "oracle_rotseq_left_d",
+                 "oracle_rotseq_left_inverse_d", "oracle_reflseq_d", "oracle_reflseq_inverse_d",
+                 "oracle_reflseq_left_d"):
         f = getattr(lib, name)
         f.restype = None
         f.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
@@ -65,34 +67,66 @@ def _ptr(arr):
     return arr.ctypes.data if arr.size else None
 
 
-def rotseq(A, C, S, *, lib=None, inverse=False, threads=None):
+def _args(A, C, S, left):
+    m, n = A.shape
+    nm1, k = C.shape
+    if S.shape != C.shape:
+        raise ValueError("C and S must have the same shape")
+    r = m if left else n  # length of the dimension the sequences mix
+    if r >= 1 and nm1 != max(r - 1, 0):
+        raise ValueError(f"C has {nm1} rows, expected {r - 1}")
+    args = (m, n, k, _ptr(A), _ld(A, "A"), _ptr(C), _ld(C, "C"), _ptr(S), _ld(S, "S"))
+    return args, (m == 0 or n == 0 or r <= 1 or k == 0)
+
+
+def rotseq(A, C, S, *, lib=None, inverse=False, threads=None, left=False):
     """Apply Algorithm 2 in place to the column-major float64 view ``A``.
 
     ``A`` is m x n, ``C`` and ``S`` are (n-1) x k.  With ``inverse=True`` the
     inverse sequence is applied instead (reverse order, transposed rotations).
     ``threads`` > 1 splits the rows across host threads (bitwise identical).
+    With ``left=True`` the rotations mix adjacent rows instead of columns
+    (C and S are (m-1) x k): A <- Q^T A, or Q A with ``inverse=True``.
     Returns ``A``.
     """
     lib = lib or _load()
-    m, n = A.shape
-    nm1, k = C.shape
-    if S.shape != C.shape:
-        raise ValueError("C and S must have the same shape")
-    if n >= 1 and nm1 != max(n - 1, 0):
-        raise ValueError(f"C has {nm1} rows, expected n-1 = {n - 1}")
-    lda = _ld(A, "A")
-    ldc = _ld(C, "C")
-    lds = _ld(S, "S")
-    args = (m, n, k, _ptr(A), lda, _ptr(C), ldc, _ptr(S), lds)
-    if m == 0 or n <= 1 or k == 0:
+    args, quick = _args(A, C, S, left)
+    if quick:
         return A
-    if inverse:
+    if left:
+        (lib.oracle_rotseq_left_inverse_d if inverse else lib.oracle_rotseq_left_d)(*args)
+    elif inverse:
         lib.oracle_rotseq_inverse_d(*args)
     elif threads and threads > 1:
         if lib.oracle_rotseq_threads_d(int(threads), *args) < 0:
             raise RuntimeError("oracle thread start failed")
     else:
         lib.oracle_rotseq_d(*args)
+    return A
+
+
+def reflseq(A, TAU, NU, *, lib=None, inverse=False, left=False):
+    """Apply a sequence of 2x2 reflectors in place to the column-major view ``A``.
+
+    Reflector (j, p) is H = I - tau v v^T with v = e_j + nu e_{j+1},
+    tau = TAU[j, p], nu = NU[j, p]; per pair w = x + nu*y, x -= tau*w,
+    y -= (tau*nu)*w.  Right application (columns j, j+1; TAU and NU are
+    (n-1) x k) in the order of Algorithm 2, or with ``inverse=True`` the same
+    reflectors in reverse order; ``left=True`` mixes rows j, j+1 instead
+    (TAU and NU are (m-1) x k).  Returns ``A``.
+    """
+    lib = lib or _load()
+    if inverse and left:
+        raise ValueError("the oracle has no left inverse reflector sequence")
+    args, quick = _args(A, TAU, NU, left)
+    if quick:
+        return A
+    if left:
+        lib.oracle_reflseq_left_d(*args)
+    elif inverse:
+        lib.oracle_reflseq_inverse_d(*args)
+    else:
+        lib.oracle_reflseq_d(*args)
     return A
 
 

@@ -23,7 +23,12 @@
  * Parity pins: every function here is pinned by CPU tests against brute
  * force (dense product of rotation matrices), exact rational arithmetic,
  * the BLAS drot routine, closed forms (swap, identity, reflection, n = 2
- * composition), norm invariants and a round trip.
+ * composition), norm invariants and a round trip.  The left application is
+ * pinned by dense products Q^T A and Q A, column-norm invariance, a row swap
+ * closed form and bitwise agreement with the right application on A^T; the
+ * reflector sequences by dense products of I - tau v v^T (orthogonal and
+ * arbitrary tau), annihilation of a row into its last entry, the tau = 0 and
+ * (tau, nu) = (2, 0) closed forms, norm invariance and a round trip.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -131,4 +136,112 @@ int oracle_rotseq_threads_d(int nthreads, int64_t m, int64_t n, int64_t k,
     for (int t = 0; t < started; ++t)
         pthread_join(tid[t], NULL);
     return started;
+}
+
+/*
+ * Left application (Section 4.3 of the paper names it as the row-wise twin of
+ * the right application, equivalently a right application to a row-major
+ * matrix).  Rotation (j, p) mixes the adjacent ROWS j and j+1 of A with the
+ * same per-pair formula as Algorithm 1; per column i:
+ *   t = c*A(j,i) + s*A(j+1,i);  A(j+1,i) = -s*A(j,i) + c*A(j+1,i);  A(j,i) = t.
+ * For p = 0..k-1, for j = 0..m-2 (the order of Algorithm 2).  In matrix form
+ *   A <- (G(0,0) G(1,0) ... G(m-2,k-1))^T A
+ * with m x m rotations G(j,p) as above; C and S are (m-1) x k.
+ */
+static void rot_rows(int64_t ncols, double *x, double *y, int64_t ld, double c, double s)
+{
+    for (int64_t i = 0; i < ncols; ++i) {
+        double t = c * x[i * ld] + s * y[i * ld];
+        y[i * ld] = -s * x[i * ld] + c * y[i * ld];
+        x[i * ld] = t;
+    }
+}
+
+void oracle_rotseq_left_d(int64_t m, int64_t n, int64_t k,
+                          double *A, int64_t lda,
+                          const double *C, int64_t ldc,
+                          const double *S, int64_t lds)
+{
+    for (int64_t p = 0; p < k; ++p)
+        for (int64_t j = 0; j + 1 < m; ++j)
+            rot_rows(n, &A[j], &A[j + 1], lda, C[j + p * ldc], S[j + p * lds]);
+}
+
+/*
+ * Inverse of oracle_rotseq_left_d: A <- G(0,0) ... G(m-2,k-1) A.  The
+ * rightmost factor acts first, and G(j,p) acting on a row pair from the left
+ * is the per-pair formula with (c, -s): p = k-1..0, j = m-2..0.
+ */
+void oracle_rotseq_left_inverse_d(int64_t m, int64_t n, int64_t k,
+                                  double *A, int64_t lda,
+                                  const double *C, int64_t ldc,
+                                  const double *S, int64_t lds)
+{
+    for (int64_t p = k - 1; p >= 0; --p)
+        for (int64_t j = m - 2; j >= 0; --j)
+            rot_rows(n, &A[j], &A[j + 1], lda, C[j + p * ldc], -S[j + p * lds]);
+}
+
+/*
+ * Sequences of 2x2 reflectors (Section 6 of the paper: a reflector plays the
+ * role of a rotation at 3 multiplications and 3 additions per entry).  The
+ * paper does not fix a parametrisation; the one read here is LAPACK's
+ * elementary reflector with unit first component:
+ *   H(j,p) = I - tau v v^T,  v = e_j + nu e_{j+1},
+ *   tau = TAU(j,p) = TAU[j + p*ldt],  nu = NU(j,p) = NU[j + p*ldn].
+ * Applied from the right to the column pair (x, y) = (A(i,j), A(i,j+1)):
+ *   w = x + nu*y;  x' = x - tau*w;  y' = y - (tau*nu)*w
+ * which is the 3 + 3 operation count (tau*nu is formed once per reflector).
+ * H is orthogonal (and its own inverse) when tau = 0 or tau*(1 + nu^2) = 2;
+ * the functions below apply the formula as written for any tau and nu.
+ */
+static void refl(int64_t len, double *x, double *y, int64_t stride, double tau, double nu)
+{
+    double tn = tau * nu;
+    for (int64_t i = 0; i < len; ++i) {
+        double w = x[i * stride] + nu * y[i * stride];
+        x[i * stride] = x[i * stride] - tau * w;
+        y[i * stride] = y[i * stride] - tn * w;
+    }
+}
+
+/* A <- A H(0,0) H(1,0) ... H(n-2,k-1), in the order of Algorithm 2. */
+void oracle_reflseq_d(int64_t m, int64_t n, int64_t k,
+                      double *A, int64_t lda,
+                      const double *TAU, int64_t ldt,
+                      const double *NU, int64_t ldn)
+{
+    for (int64_t p = 0; p < k; ++p)
+        for (int64_t j = 0; j + 1 < n; ++j)
+            refl(m, &A[j * lda], &A[(j + 1) * lda], 1, TAU[j + p * ldt], NU[j + p * ldn]);
+}
+
+/*
+ * A <- A H(n-2,k-1) ... H(0,0): the same reflectors in reverse order
+ * (p = k-1..0, j = n-2..0).  For orthogonal reflectors (H^-1 = H^T = H) this
+ * undoes oracle_reflseq_d.
+ */
+void oracle_reflseq_inverse_d(int64_t m, int64_t n, int64_t k,
+                              double *A, int64_t lda,
+                              const double *TAU, int64_t ldt,
+                              const double *NU, int64_t ldn)
+{
+    for (int64_t p = k - 1; p >= 0; --p)
+        for (int64_t j = n - 2; j >= 0; --j)
+            refl(m, &A[j * lda], &A[(j + 1) * lda], 1, TAU[j + p * ldt], NU[j + p * ldn]);
+}
+
+/*
+ * Reflectors mixing adjacent ROWS: the per-pair formula above with
+ * (x, y) = (A(j,i), A(j+1,i)) for every column i, p = 0..k-1, j = 0..m-2;
+ * A <- (H(0,0) ... H(m-2,k-1))^T A.  TAU and NU are (m-1) x k.
+ */
+void oracle_reflseq_left_d(int64_t m, int64_t n, int64_t k,
+                           double *A, int64_t lda,
+                           const double *TAU, int64_t ldt,
+                           const double *NU, int64_t ldn)
+{
+    for (int64_t p = 0; p < k; ++p)
+        for (int64_t j = 0; j + 1 < m; ++j)
+            refl(n, &A[j], &A[j + 1], lda, TAU[j + p * ldt], NU[j + p * ldn]);
 }

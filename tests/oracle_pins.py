@@ -295,3 +295,198 @@ ALL_PINS = [
     pin_row_independence,
     pin_hand_worked,
 ]
+
+
+# ------------------------------------------------- left application pins
+#
+# Each takes ``apply_left(A, C, S, inverse=False)``: rotations mixing the
+# adjacent rows j, j+1 of A with the per-pair formula of Algorithm 1, in the
+# order of Algorithm 2; C and S are (m-1) x k.  In matrix form A <- Q^T A
+# (Q the m x m product of the G(j,p) as above), and Q A for the inverse.
+
+def pin_left_dense(apply_left):
+    """L-1: Q^T A and Q A computed densely (m != n, padded leading dims)."""
+    rng = np.random.Generator(np.random.PCG64(201))
+    for idx, (m, n, k) in enumerate([(2, 1, 1), (2, 5, 3), (5, 3, 2), (7, 4, 5), (9, 12, 3)]):
+        th = rng.uniform(0, 2 * math.pi, (m - 1, k))
+        A = colmajor(rng.standard_normal((m, n)), m + idx % 2)
+        C, S = colmajor(np.cos(th), m - 1 + idx % 3), colmajor(np.sin(th))
+        Q = dense_q(np.asarray(C), np.asarray(S), m)
+        A0 = np.array(A)
+        pad = _padding(A)
+        apply_left(A, C, S)
+        e = relerr(A, Q.T @ A0)
+        assert e <= 1e-14, f"left vs dense m={m} n={n} k={k}: rel err {e:.3e}"
+        assert np.array_equal(_padding(A), pad), "padding rows of A were modified"
+        apply_left(A, C, S, inverse=True)
+        e = relerr(A, A0)
+        assert e <= 1e-14, f"left round trip m={m} n={n} k={k}: rel err {e:.3e}"
+        B = colmajor(A0)
+        apply_left(B, C, S, inverse=True)
+        e = relerr(B, Q @ A0)
+        assert e <= 1e-14, f"left inverse vs dense m={m} n={n} k={k}: rel err {e:.3e}"
+
+
+def pin_left_is_right_on_transpose(apply_left, apply_right):
+    """L-2: rotating rows of A is rotating columns of A^T with the same
+    per-pair formula, entry for entry, so the two agree bitwise (ties the
+    left application to the pinned right application)."""
+    rng = np.random.Generator(np.random.PCG64(202))
+    for (m, n, k) in [(6, 4, 3), (13, 9, 7), (2, 3, 4)]:
+        th = rng.uniform(0, 2 * math.pi, (m - 1, k))
+        A0 = rng.standard_normal((m, n))
+        C, S = colmajor(np.cos(th)), colmajor(np.sin(th))
+        A = colmajor(A0)
+        apply_left(A, C, S)
+        T = colmajor(A0.T.copy())
+        apply_right(T, C, S)
+        assert np.array_equal(np.asarray(A), np.asarray(T).T), f"left != right on A^T m={m} n={n}"
+
+
+def pin_left_column_norms(apply_left):
+    """L-3: rotations from the left keep every column's 2-norm; the rows
+    swap closed form c = 0, s = 1 shifts rows up cyclically with the wrapped
+    row picking up (-1)^(m-1) per sequence."""
+    rng = np.random.Generator(np.random.PCG64(203))
+    m, n, k = 21, 8, 11
+    th = rng.uniform(0, 2 * math.pi, (m - 1, k))
+    A = colmajor(rng.standard_normal((m, n)))
+    before = np.linalg.norm(np.asarray(A), axis=0)
+    apply_left(A, colmajor(np.cos(th)), colmajor(np.sin(th)))
+    dev = np.max(np.abs(np.linalg.norm(np.asarray(A), axis=0) - before) / before)
+    assert dev <= 6 * U * (m - 1) * k, f"column norm deviation {dev:.3e}"
+    m, n, k = 5, 3, 2
+    A0 = rng.standard_normal((m, n))
+    ref = A0.copy()
+    for _ in range(k):
+        first = ref[0].copy()
+        ref[:-1] = ref[1:]
+        ref[-1] = first * (-1.0) ** (m - 1)
+    A = colmajor(A0)
+    apply_left(A, colmajor(np.zeros((m - 1, k))), colmajor(np.ones((m - 1, k))))
+    assert np.array_equal(np.asarray(A), ref), "left swap closed form"
+
+
+LEFT_PINS = [pin_left_dense, pin_left_column_norms]
+
+
+# ------------------------------------------------------- reflector pins
+#
+# Each takes ``apply_refl(A, TAU, NU, inverse=False, left=False)``.  The
+# reflector (j, p) is H = I - tau v v^T with v = e_j + nu e_{j+1}.
+
+def dense_h(TAU, NU, n):
+    """prod_p prod_j H(j, p) in Algorithm 2's order, as a dense matrix."""
+    Q = np.eye(n)
+    nm1, k = TAU.shape
+    for p in range(k):
+        for j in range(nm1):
+            v = np.zeros(n)
+            v[j] = 1.0
+            v[j + 1] = NU[j, p]
+            Q = Q @ (np.eye(n) - TAU[j, p] * np.outer(v, v))
+    return Q
+
+
+def orthogonal_reflectors(rng, r, k):
+    """tau = 2 / (1 + nu^2): every H is orthogonal (a true reflection)."""
+    nu = rng.standard_normal((r, k)) * rng.choice([0.1, 1.0, 10.0], (r, k))
+    return 2.0 / (1.0 + nu * nu), nu
+
+
+def pin_refl_dense(apply_refl):
+    """R-1: A H(0,0)...H(n-2,k-1) densely, for orthogonal and for arbitrary
+    (tau, nu) (the formula is applied as written either way); the reverse
+    order densely; rows from the left as (prod H)^T A."""
+    rng = np.random.Generator(np.random.PCG64(301))
+    for idx, (m, n, k) in enumerate([(1, 2, 1), (4, 3, 2), (5, 7, 3), (3, 9, 4)]):
+        for ortho in (True, False):
+            if ortho:
+                tau, nu = orthogonal_reflectors(rng, n - 1, k)
+            else:
+                tau, nu = rng.uniform(-0.5, 2.5, (n - 1, k)), rng.standard_normal((n - 1, k))
+            A0 = rng.standard_normal((m, n))
+            H = dense_h(tau, nu, n)
+            A = colmajor(A0, m + idx % 2)
+            pad = _padding(A)
+            apply_refl(A, colmajor(tau, n - 1 + idx % 3), colmajor(nu))
+            e = relerr(A, A0 @ H)
+            assert e <= 1e-13, f"reflectors vs dense m={m} n={n} k={k} ortho={ortho}: {e:.3e}"
+            assert np.array_equal(_padding(A), pad), "padding rows of A were modified"
+            Hr = np.eye(n)
+            for p in reversed(range(k)):
+                for j in reversed(range(n - 1)):
+                    v = np.zeros(n)
+                    v[j], v[j + 1] = 1.0, nu[j, p]
+                    Hr = Hr @ (np.eye(n) - tau[j, p] * np.outer(v, v))
+            A = colmajor(A0)
+            apply_refl(A, colmajor(tau), colmajor(nu), inverse=True)
+            e = relerr(A, A0 @ Hr)
+            assert e <= 1e-13, f"reverse reflectors vs dense m={m} n={n} k={k}: {e:.3e}"
+            B0 = rng.standard_normal((n, m))
+            B = colmajor(B0)
+            apply_refl(B, colmajor(tau), colmajor(nu), left=True)
+            e = relerr(B, H.T @ B0)
+            assert e <= 1e-13, f"left reflectors vs dense n={n} k={k}: {e:.3e}"
+
+
+def pin_refl_norm_transfer(apply_refl):
+    """R-2: reflectors built from the row itself push its whole norm into the
+    last column.  For the pair (x, y), nu = (y + sign(y) r) / x with
+    r = hypot(x, y) and tau = 2 / (1 + nu^2) solve [x y] H = [0, +-r]
+    (a root of x nu^2 - 2 y nu - x = 0); x = 0 needs tau = 0."""
+    rng = np.random.Generator(np.random.PCG64(302))
+    n = 9
+    row = rng.standard_normal(n)
+    row[0] = 0.0  # the first pair needs no reflection: tau = 0
+    tau, nu = np.zeros((n - 1, 1)), np.zeros((n - 1, 1))
+    x = row.copy()
+    for j in range(n - 1):
+        a, b = x[j], x[j + 1]
+        r = math.hypot(a, b)
+        if a == 0.0:
+            t, v = 0.0, 0.0
+        else:
+            v = (b + math.copysign(r, b)) / a
+            t = 2.0 / (1.0 + v * v)
+        tau[j, 0], nu[j, 0] = t, v
+        # exact image of the pair under H (the orthogonal reflector maps it to (0, +-r))
+        x[j], x[j + 1] = 0.0, (-math.copysign(r, b) if a != 0.0 else b)
+    A = colmajor(row[None, :])
+    apply_refl(A, colmajor(tau), colmajor(nu))
+    out = np.asarray(A)[0]
+    nrm = float(np.linalg.norm(row))
+    assert np.max(np.abs(out[:-1])) <= 40 * n * U * nrm, f"entries not annihilated: {out[:-1]}"
+    assert abs(out[-1] - x[-1]) <= 40 * n * U * nrm, f"last entry {out[-1]} != {x[-1]}"
+
+
+def pin_refl_closed_forms(apply_refl):
+    """R-3: tau = 0 is the identity (bitwise); (tau, nu) = (2, 0) is
+    diag(-1, 1) on the pair, so one sequence negates columns 0..n-2 once each
+    and k sequences multiply them by (-1)^k (exact); orthogonal reflectors
+    keep row norms and the reverse order undoes the forward order."""
+    rng = np.random.Generator(np.random.PCG64(303))
+    m, n, k = 4, 6, 3
+    A0 = rng.standard_normal((m, n))
+    A = colmajor(A0)
+    apply_refl(A, colmajor(np.zeros((n - 1, k))), colmajor(rng.standard_normal((n - 1, k))))
+    assert np.array_equal(np.asarray(A), A0), "tau = 0 changed A"
+    A = colmajor(A0)
+    apply_refl(A, colmajor(np.full((n - 1, k), 2.0)), colmajor(np.zeros((n - 1, k))))
+    ref = A0.copy()
+    ref[:, :-1] *= (-1.0) ** k
+    assert np.array_equal(np.asarray(A), ref), "(tau, nu) = (2, 0) closed form"
+    m, n, k = 9, 23, 8
+    tau, nu = orthogonal_reflectors(rng, n - 1, k)
+    A0 = rng.standard_normal((m, n))
+    A = colmajor(A0)
+    apply_refl(A, colmajor(tau), colmajor(nu))
+    dev = np.max(np.abs(np.linalg.norm(np.asarray(A), axis=1) / np.linalg.norm(A0, axis=1) - 1))
+    assert dev <= 40 * U * (n - 1) * k, f"row norm deviation {dev:.3e}"
+    assert relerr(np.asarray(A), A0) > 1e-3
+    apply_refl(A, colmajor(tau), colmajor(nu), inverse=True)
+    e = relerr(A, A0)
+    assert e <= 40 * U * (n - 1) * k, f"reflector round trip {e:.3e}"
+
+
+REFL_PINS = [pin_refl_dense, pin_refl_norm_transfer, pin_refl_closed_forms]

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from oracle import build as obuild
-from oracle_pins import ALL_PINS
+from oracle_pins import ALL_PINS, LEFT_PINS, REFL_PINS, pin_left_is_right_on_transpose
 
 FWD_LOOP = ("    for (int64_t p = 0; p < k; ++p)\n"
             "        for (int64_t j = 0; j + 1 < n; ++j)\n"
@@ -43,6 +43,44 @@ MUTANTS = {
 }
 
 
+LEFT_LOOP = ("        for (int64_t j = 0; j + 1 < m; ++j)\n"
+             "            rot_rows(n, &A[j], &A[j + 1], lda, C[j + p * ldc], S[j + p * lds]);")
+
+# Mutants of the left-application functions, caught by the left pins.
+LEFT_MUTANTS = {
+    "left_y_sign": ("y[i * ld] = -s * x[i * ld] + c * y[i * ld];",
+                    "y[i * ld] = s * x[i * ld] + c * y[i * ld];"),
+    "left_unit_stride": ("double t = c * x[i * ld] + s * y[i * ld];\n        y[i * ld] = -s * x[i * ld] + c * y[i * ld];\n        x[i * ld] = t;",
+                         "double t = c * x[i] + s * y[i];\n        y[i] = -s * x[i] + c * y[i];\n        x[i] = t;"),
+    "left_bound_uses_n": (LEFT_LOOP, LEFT_LOOP.replace("j + 1 < m", "j + 1 < n")),
+    "left_row_roles_swapped": (LEFT_LOOP, LEFT_LOOP.replace("rot_rows(n, &A[j], &A[j + 1], lda",
+                                                            "rot_rows(n, &A[j + 1], &A[j], lda")),
+    "left_inverse_not_transposed": ("rot_rows(n, &A[j], &A[j + 1], lda, C[j + p * ldc], -S[j + p * lds]);",
+                                    "rot_rows(n, &A[j], &A[j + 1], lda, C[j + p * ldc], S[j + p * lds]);"),
+}
+
+REFL_FWD = ("refl(m, &A[j * lda], &A[(j + 1) * lda], 1, TAU[j + p * ldt], NU[j + p * ldn]);")
+
+# Mutants of the reflector functions, caught by the reflector pins.
+REFL_MUTANTS = {
+    "refl_w_roles_swapped": ("double w = x[i * stride] + nu * y[i * stride];",
+                             "double w = nu * x[i * stride] + y[i * stride];"),
+    "refl_x_sign": ("x[i * stride] = x[i * stride] - tau * w;", "x[i * stride] = x[i * stride] + tau * w;"),
+    "refl_y_drops_nu": ("double tn = tau * nu;", "double tn = tau;"),
+    "refl_y_uses_nu_squared": ("double tn = tau * nu;", "double tn = tau * nu * nu;"),
+    "refl_w_uses_new_x": ("        double w = x[i * stride] + nu * y[i * stride];\n        x[i * stride] = x[i * stride] - tau * w;\n        y[i * stride] = y[i * stride] - tn * w;",
+                          "        double w = x[i * stride] + nu * y[i * stride];\n        x[i * stride] = x[i * stride] - tau * w;\n        y[i * stride] = y[i * stride] - tn * (x[i * stride] + nu * y[i * stride]);"),
+    "refl_tau_nu_swapped": (REFL_FWD, REFL_FWD.replace("TAU[j + p * ldt], NU[j + p * ldn]", "NU[j + p * ldn], TAU[j + p * ldt]")),
+    "refl_inverse_forward_order": ("    for (int64_t p = k - 1; p >= 0; --p)\n"
+                                   "        for (int64_t j = n - 2; j >= 0; --j)\n"
+                                   "            refl(",
+                                   "    for (int64_t p = 0; p < k; ++p)\n"
+                                   "        for (int64_t j = 0; j + 1 < n; ++j)\n"
+                                   "            refl("),
+    "refl_left_wrong_stride": ("refl(n, &A[j], &A[j + 1], lda,", "refl(n, &A[j], &A[j + 1], 1,"),
+}
+
+
 @pytest.fixture(scope="module")
 def source():
     with open(os.path.join(os.path.dirname(oracle.__file__), "rotseq_oracle.c")) as f:
@@ -68,3 +106,50 @@ def test_mutant_is_caught(name, source, tmp_path):
         except AssertionError as e:
             failed.append((pin.__name__, str(e)[:80]))
     assert failed, f"mutant {name} passed every pin"
+
+
+def _mutant_lib(source, tmp_path, old, new, name):
+    assert source.count(old) >= 1, f"mutation site for {name} not found"
+    src = tmp_path / "mutant.c"
+    src.write_text(source.replace(old, new, 1))
+    return oracle._load(obuild.build(str(src), str(tmp_path / "libmutant.so"),
+                                     extra=["-Wno-unused-variable", "-Wno-unused-but-set-variable",
+                                            "-Wno-unused-parameter"]))
+
+
+def _fails_some(pins, *fns):
+    failed = []
+    for pin in pins:
+        try:
+            pin(*fns)
+        except AssertionError as e:
+            failed.append((pin.__name__, str(e)[:80]))
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(LEFT_MUTANTS))
+def test_left_mutant_is_caught(name, source, tmp_path):
+    lib = _mutant_lib(source, tmp_path, *LEFT_MUTANTS[name], name)
+
+    def left(A, C, S, inverse=False):
+        oracle.rotseq(A, C, S, inverse=inverse, left=True, lib=lib)
+
+    def right(A, C, S, inverse=False):
+        oracle.rotseq(A, C, S, inverse=inverse, lib=lib)
+
+    failed = _fails_some(LEFT_PINS, left)
+    try:
+        pin_left_is_right_on_transpose(left, right)
+    except AssertionError as e:
+        failed.append(("pin_left_is_right_on_transpose", str(e)[:80]))
+    assert failed, f"mutant {name} passed every left pin"
+
+
+@pytest.mark.parametrize("name", sorted(REFL_MUTANTS))
+def test_refl_mutant_is_caught(name, source, tmp_path):
+    lib = _mutant_lib(source, tmp_path, *REFL_MUTANTS[name], name)
+
+    def refl(A, TAU, NU, inverse=False, left=False):
+        oracle.reflseq(A, TAU, NU, inverse=inverse, left=left, lib=lib)
+
+    assert _fails_some(REFL_PINS, refl), f"mutant {name} passed every reflector pin"

@@ -4,7 +4,8 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle_pins import ALL_PINS, colmajor, rand_problem
+from oracle_pins import (ALL_PINS, LEFT_PINS, REFL_PINS, colmajor, pin_left_is_right_on_transpose,
+                         rand_problem)
 
 
 def oracle_apply(A, C, S, inverse=False):
@@ -41,3 +42,25 @@ def test_quick_returns():
     before = np.array(A)
     oracle.rotseq(A, C, S)
     assert np.array_equal(np.asarray(A), before)
+
+
+def oracle_left(A, C, S, inverse=False):
+    oracle.rotseq(A, C, S, inverse=inverse, left=True)
+
+
+def oracle_refl(A, TAU, NU, inverse=False, left=False):
+    oracle.reflseq(A, TAU, NU, inverse=inverse, left=left)
+
+
+@pytest.mark.parametrize("pin", LEFT_PINS, ids=lambda p: p.__name__)
+def test_left_pin(pin):
+    pin(oracle_left)
+
+
+def test_left_is_right_on_transpose():
+    pin_left_is_right_on_transpose(oracle_left, oracle_apply)
+
+
+@pytest.mark.parametrize("pin", REFL_PINS, ids=lambda p: p.__name__)
+def test_refl_pin(pin):
+    pin(oracle_refl)
