@@ -94,6 +94,21 @@ extern "C" {
  *           i.e. the rotations in reverse order (p and j descending) with
  *           s negated; it undoes a forward call up to rounding.  In
  *           exact mode it equals that loop bitwise.  Not for batches.
+ *   left    nonzero: the rotations mix adjacent ROWS of A instead of
+ *           columns (application from the left, Section 4.3 of the paper).
+ *           A is still m x n column-major with lda >= max(1,m), but C and S
+ *           are (m-1) x k (ldc, lds >= max(1,m-1)), and rotation (j,p)
+ *           applies the same per-pair formula to x = A(j,i), y = A(j+1,i)
+ *           for every column i, in the order of Algorithm 2:
+ *               A <- (G(0,0) ... G(m-2,k-1))^T A     (m x m rotations),
+ *           and with `inverse` A <- G(0,0) ... G(m-2,k-1) A.
+ *           A right application to a row-major r x q matrix B (row stride
+ *           ldb) is a left application to the column-major q x r matrix
+ *           with leading dimension ldb that is the same memory.
+ *           The library packs A transposed into the workspace (m*n more
+ *           elements, see rotseq_workspace_bytes), sweeps the packed copy
+ *           and unpacks it.  Quick return if n == 0, m <= 1 or k == 0.
+ *           Not for batches.
  */
 typedef struct rotseq_opts {
     int32_t arith;
@@ -102,7 +117,8 @@ typedef struct rotseq_opts {
     int32_t waves;
     int32_t publish;
     int32_t inverse;
-    int32_t reserved[2];
+    int32_t left;
+    int32_t reserved;
 } rotseq_opts;
 
 /*
@@ -149,9 +165,40 @@ int rotseq_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
                 void *workspace, size_t ws_bytes);
 
 /*
- * Device workspace bytes needed by rotseq_ex_{d,s} for this shape and
- * options; dtype is 'd' or 's'.  Returns 0 for quick-return shapes and for
- * invalid arguments.  Host-only; never touches the GPU.
+ * rotseq_refl_ex_d / rotseq_refl_ex_s: sequences of 2x2 reflectors instead
+ * of rotations (Section 6 of the paper: a reflector does the job of a
+ * rotation with 3 multiplications and 3 additions per entry).  Reflector
+ * (j,p) is LAPACK's elementary reflector with unit first component,
+ *     H(j,p) = I - tau v v^T,   v = e_j + nu e_{j+1},
+ *     tau = TAU(j,p) = TAU[j + p*ldt],  nu = NU(j,p) = NU[j + p*ldn],
+ * and the call computes A <- A H(0,0) H(1,0) ... H(n-2,k-1) (per row:
+ * w = x + nu*y, x' = x - tau*w, y' = y - tau*nu*w on columns j, j+1).
+ * Arguments 1-13 as for rotseq_ex_d with TAU, ldt, NU, ldn in place of
+ * C, ldc, S, lds; `opts` may ask for the inverse order (the same reflectors
+ * with p and j descending) and for left application (rows j, j+1; TAU and
+ * NU are then (m-1) x k).
+ * Every reflector must be orthogonal: tau = 0 (the identity) or
+ * tau * (1 + nu^2) = 2 up to rounding, as LAPACK's dlarfg produces.  The
+ * library applies each one as a rotation followed by negating one column
+ * (the negations are tracked and undone as in ROTSEQ_ARITH_LIFT), so
+ * other values give results that are not A H.  This is not checked.
+ * Only ROTSEQ_ARITH_AUTO / ROTSEQ_ARITH_LIFT are supported
+ * (ROTSEQ_E_UNSUPPORTED otherwise).  Workspace as for rotseq_ex_d.
+ */
+int rotseq_refl_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
+                     const double *TAU, int64_t ldt, const double *NU, int64_t ldn,
+                     hipStream_t stream, const rotseq_opts *opts,
+                     void *workspace, size_t ws_bytes);
+int rotseq_refl_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
+                     const float *TAU, int64_t ldt, const float *NU, int64_t ldn,
+                     hipStream_t stream, const rotseq_opts *opts,
+                     void *workspace, size_t ws_bytes);
+
+/*
+ * Device workspace bytes needed by rotseq_ex_{d,s} and rotseq_refl_ex_{d,s}
+ * for this shape and options; dtype is 'd' or 's'.  Returns 0 for
+ * quick-return shapes and for invalid arguments.  Host-only; never touches
+ * the GPU.
  */
 size_t rotseq_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k,
                               const rotseq_opts *opts);

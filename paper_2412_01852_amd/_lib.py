@@ -28,7 +28,7 @@ class Options(ctypes.Structure):
     _fields_ = [("arith", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("publish", ctypes.c_int32), ("inverse", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("left", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -108,7 +108,7 @@ def _load():
     for name in ("rotseq_d", "rotseq_s"):
         f = getattr(lib, name)
         f.restype, f.argtypes = i32, base
-    for name in ("rotseq_ex_d", "rotseq_ex_s"):
+    for name in ("rotseq_ex_d", "rotseq_ex_s", "rotseq_refl_ex_d", "rotseq_refl_ex_s"):
         f = getattr(lib, name)
         f.restype, f.argtypes = i32, base + [ctypes.POINTER(Options), vp, ctypes.c_size_t]
     lib.rotseq_workspace_bytes.restype = ctypes.c_size_t
@@ -198,23 +198,44 @@ def _ld(t, name):
     return t.stride(1)
 
 
+def _is_left(opts):
+    if opts is None:
+        return False
+    if isinstance(opts, Options):
+        return bool(opts.left)
+    return bool(dict(opts).get("left", 0))
+
+
 def rotseq(A, C, S, *, opts=None, workspace=None, stream=None):
     """A <- A * G(0,0) ... G(n-2,k-1) in place on the GPU (Algorithms 1-2).
 
     A: (m, n) float64/float32 column-major device tensor; C, S: (n-1, k) of the
-    same dtype.  ``opts`` is an Options or a dict of its fields; ``workspace``
-    an optional uint8 device tensor; ``stream`` a torch stream (default: the
-    current one).  Returns A.
+    same dtype ((m-1, k) with ``opts["left"]``, rotations mixing rows).
+    ``opts`` is an Options or a dict of its fields; ``workspace`` an optional
+    uint8 device tensor; ``stream`` a torch stream (default: the current
+    one).  Returns A.
     """
+    return _call(False, A, C, S, opts, workspace, stream)
+
+
+def reflseq(A, TAU, NU, *, opts=None, workspace=None, stream=None):
+    """A <- A * H(0,0) ... H(n-2,k-1) for 2x2 reflectors H = I - tau v v^T,
+    v = e_j + nu e_{j+1} (rotseq_refl_ex_*); arguments as for rotseq with
+    TAU, NU in place of C, S."""
+    return _call(True, A, TAU, NU, opts, workspace, stream)
+
+
+def _call(refl, A, C, S, opts, workspace, stream):
     import torch
     if A.dtype not in (torch.float64, torch.float32):
         raise TypeError("A must be float64 or float32")
     if C.dtype != A.dtype or S.dtype != A.dtype:
-        raise TypeError("A, C and S must share a dtype")
+        raise TypeError("A and the coefficient arrays must share a dtype")
     m, n = A.shape
     k = C.shape[1]
-    if C.shape != S.shape or C.shape[0] != max(n - 1, 0):
-        raise ValueError(f"C and S must be ({max(n - 1, 0)}, k); got {tuple(C.shape)}, {tuple(S.shape)}")
+    r = m if _is_left(opts) else n
+    if C.shape != S.shape or C.shape[0] != max(r - 1, 0):
+        raise ValueError(f"coefficient arrays must be ({max(r - 1, 0)}, k); got {tuple(C.shape)}, {tuple(S.shape)}")
     for t, nm in ((A, "A"), (C, "C"), (S, "S")):
         if t.numel() and not t.is_cuda:
             raise ValueError(f"{nm} must be a device tensor")
@@ -224,16 +245,19 @@ def rotseq(A, C, S, *, opts=None, workspace=None, stream=None):
     ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
     lib = _load()
     dbl = A.dtype == torch.float64
-    if opts is None and workspace is None:
+    if opts is None and workspace is None and not refl:
         fn = lib.rotseq_d if dbl else lib.rotseq_s
         rc = fn(m, n, k, ptr(A), lda, ptr(C), ldc, ptr(S), lds, handle)
     else:
-        fn = lib.rotseq_ex_d if dbl else lib.rotseq_ex_s
+        if refl:
+            fn = lib.rotseq_refl_ex_d if dbl else lib.rotseq_refl_ex_s
+        else:
+            fn = lib.rotseq_ex_d if dbl else lib.rotseq_ex_s
         wptr = workspace.data_ptr() if workspace is not None else None
         wbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
         rc = fn(m, n, k, ptr(A), lda, ptr(C), ldc, ptr(S), lds, handle, _opts(opts), wptr, wbytes)
     if rc != 0:
-        raise RotseqError(rc, "rotseq")
+        raise RotseqError(rc, "reflseq" if refl else "rotseq")
     return A
 
 

@@ -187,7 +187,7 @@ int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_
     int arith = 0, band = 0, kernel = 0;
     if (!resolve_opts(opts, arith, band, kernel))
         return ROTSEQ_E_UNSUPPORTED;
-    if ((kernel != 0 && kernel != kChain) || (opts && opts->inverse))
+    if ((kernel != 0 && kernel != kChain) || (opts && (opts->inverse || opts->left)))
         return ROTSEQ_E_UNSUPPORTED;
     if (band == 0)
         band = 8;

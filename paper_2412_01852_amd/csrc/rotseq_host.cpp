@@ -187,8 +187,10 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
 namespace {
 
 
+// Argument check of rotseq_d; `left`: the sequences mix rows, so C and S
+// have m-1 rows and there is work only for n > 0, m > 1.
 int check_args(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *C,
-               int64_t ldc, const void *S, int64_t lds)
+               int64_t ldc, const void *S, int64_t lds, bool left = false)
 {
     if (m < 0)
         return -1;
@@ -196,8 +198,9 @@ int check_args(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, cons
         return -2;
     if (k < 0)
         return -3;
-    const bool work = m > 0 && n > 1 && k > 0;
-    const int64_t n1 = n > 1 ? n - 1 : 1;
+    const int64_t r = left ? m : n;  // length of the dimension the sequences mix
+    const bool work = (left ? n > 0 : m > 0) && r > 1 && k > 0;
+    const int64_t n1 = r > 1 ? r - 1 : 1;
     if (work && A == nullptr)
         return -4;
     if (lda < (m > 1 ? m : 1))
@@ -258,8 +261,10 @@ Pool &pool()
 struct Profiler {
     std::atomic<bool> on{false};
     std::mutex mu;
+    // e0..e1: packing of A (left application) and coefficient preparation;
+    // e1..e2: the sweep; e2..e3: unpacking.
     struct Rec {
-        hipEvent_t e0, e1, e2;
+        hipEvent_t e0, e1, e2, e3;
     };
     std::vector<Rec> pending;
     rotseq_profile acc{};
@@ -272,6 +277,7 @@ struct Profiler {
             return false;
         (void)hipEventCreate(&r.e1);
         (void)hipEventCreate(&r.e2);
+        (void)hipEventCreate(&r.e3);
         (void)hipEventRecord(r.e0, st);
         return true;
     }
@@ -285,12 +291,13 @@ struct Profiler {
         std::lock_guard<std::mutex> lock(mu);
         int rc = ROTSEQ_SUCCESS;
         for (const Rec &r : pending) {
-            float a = 0.f, b = 0.f;
-            if (hipEventSynchronize(r.e2) != hipSuccess ||
+            float a = 0.f, b = 0.f, c = 0.f;
+            if (hipEventSynchronize(r.e3) != hipSuccess ||
                 hipEventElapsedTime(&a, r.e0, r.e1) != hipSuccess ||
-                hipEventElapsedTime(&b, r.e1, r.e2) != hipSuccess)
+                hipEventElapsedTime(&b, r.e1, r.e2) != hipSuccess ||
+                hipEventElapsedTime(&c, r.e2, r.e3) != hipSuccess)
                 rc = ROTSEQ_E_HIP;
-            acc.prep_ms += a;
+            acc.prep_ms += a + c;
             acc.sweep_ms += b;
             acc.sweep_ms_min = acc.calls ? std::min(acc.sweep_ms_min, (double)b) : b;
             acc.sweep_ms_max = acc.calls ? std::max(acc.sweep_ms_max, (double)b) : b;
@@ -298,6 +305,7 @@ struct Profiler {
             (void)hipEventDestroy(r.e0);
             (void)hipEventDestroy(r.e1);
             (void)hipEventDestroy(r.e2);
+            (void)hipEventDestroy(r.e3);
         }
         pending.clear();
         if (out)
@@ -331,53 +339,58 @@ bool resolve(const rotseq_opts *opts, int &arith, int &band, int &kernel)
     return true;
 }
 
+// Plan of the sweep over the matrix whose columns the sequences mix: A
+// itself (m x n), or for left application A^T (n x m) packed into the
+// workspace after the plan's own buffers (off_pack, leading dimension n).
 bool plan_for(Plan &p, int esize, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldc,
-              int64_t lds, const rotseq_opts *opts)
+              int64_t lds, const rotseq_opts *opts, int kind, size_t &off_pack)
 {
     int arith = 0, band = 0, kernel = 0;
     if (!resolve(opts, arith, band, kernel))
         return false;
+    // Reflectors are applied as rotations plus tracked column negations,
+    // which only the lifting form carries.
+    if (kind != kRotate && arith != kLift)
+        return false;
+    const bool left = opts && opts->left;
     p = Plan{};
-    p.m = m;
-    p.n = n;
+    p.m = left ? n : m;
+    p.n = left ? m : n;
     p.k = k;
-    p.lda = lda;
+    p.lda = left ? p.m : lda;
     p.ldc = ldc;
     p.lds = lds;
     p.cstep = 1;
     p.arith = arith;
+    p.kind = kind;
     p.esize = esize;
-    return make_plan(p, kernel, band);
+    if (!make_plan(p, kernel, band))
+        return false;
+    off_pack = 0;
+    if (left) {
+        off_pack = p.total;
+        p.total = align256(p.total + (size_t)p.m * (size_t)p.n * (size_t)esize);
+    }
+    return true;
 }
 
 template <typename T>
-int run(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C, int64_t ldc, const T *S,
-        int64_t lds, hipStream_t stream, const rotseq_opts *opts, void *ws, size_t ws_bytes)
+int run(int kind, int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C, int64_t ldc,
+        const T *S, int64_t lds, hipStream_t stream, const rotseq_opts *opts, void *ws,
+        size_t ws_bytes)
 {
-    const int bad = check_args(m, n, k, A, lda, C, ldc, S, lds);
+    const bool left = opts && opts->left;
+    const int bad = check_args(m, n, k, A, lda, C, ldc, S, lds, left);
     if (bad)
         return bad;
-    if (m == 0 || n <= 1 || k == 0)
+    if ((left ? n == 0 || m <= 1 : m == 0 || n <= 1) || k == 0)
         return ROTSEQ_SUCCESS;
     Plan p;
-    if (!plan_for(p, (int)sizeof(T), m, n, k, lda, ldc, lds, opts))
+    size_t off_pack = 0;
+    if (!plan_for(p, (int)sizeof(T), m, n, k, lda, ldc, lds, opts, kind, off_pack))
         return ROTSEQ_E_UNSUPPORTED;
-    if (n > INT32_MAX - 64 || p.steps <= 0)
+    if (p.n > INT32_MAX - 64 || p.steps <= 0)
         return ROTSEQ_E_UNSUPPORTED;
-    if (opts && opts->inverse) {
-        // The inverse applies, for p = k-1..0 and j = n-2..0, the rotation
-        // (c, -s) to columns (j, j+1).  On the column-reversed matrix
-        // A'(:, i) = A(:, n-1-i) that is the rotation (c, s) on columns
-        // (n-2-j, n-1-j) in the forward order of Algorithm 2, with
-        // C'(i, q) = C(n-2-i, k-1-q): a forward call on reversed views.
-        A += (n - 1) * lda;
-        p.lda = -lda;
-        C += (n - 2) + (k - 1) * ldc;
-        S += (n - 2) + (k - 1) * lds;
-        p.ldc = -ldc;
-        p.lds = -lds;
-        p.cstep = -1;
-    }
     if (configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (ws) {
@@ -388,16 +401,45 @@ int run(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C, int64_t 
         if (rc)
             return rc;
     }
+    // X: the p.m x p.n matrix the sweep runs on (A, or the packed A^T).
+    T *X = left ? (T *)((char *)ws + off_pack) : A;
     Profiler::Rec rec{};
     const bool timed = profiler().begin(rec, stream);
+    if (left && launch_transpose(A, m, n, lda, X, p.lda, (int)sizeof(T), stream) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (opts && opts->inverse) {
+        // The inverse applies, for p = k-1..0 and j = n-2..0, the rotation
+        // (c, -s) to columns (j, j+1).  On the column-reversed matrix
+        // A'(:, i) = A(:, n-1-i) that is the rotation (c, s) on columns
+        // (n-2-j, n-1-j) in the forward order of Algorithm 2, with
+        // C'(i, q) = C(n-2-i, k-1-q): a forward call on reversed views.
+        // A reflector is its own inverse, so the inverse of a reflector
+        // sequence is the same reflectors in reverse order; on the reversed
+        // matrix each one reads as kReflectRev (see pair_rotation).
+        const int64_t rn = p.n, ld = p.lda;
+        X += (rn - 1) * ld;
+        p.lda = -ld;
+        C += (rn - 2) + (k - 1) * ldc;
+        S += (rn - 2) + (k - 1) * lds;
+        p.ldc = -ldc;
+        p.lds = -lds;
+        p.cstep = -1;
+        if (p.kind == kReflect)
+            p.kind = kReflectRev;
+    }
     if (launch_prep(p, C, S, ws, stream) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (timed)
         (void)hipEventRecord(rec.e1, stream);
-    if (launch_sweep(p, A, ws, stream) != hipSuccess)
+    if (launch_sweep(p, X, ws, stream) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (timed)
+        (void)hipEventRecord(rec.e2, stream);
+    if (left && launch_transpose((const char *)ws + off_pack, p.m, p.n, p.m, A, lda, (int)sizeof(T),
+                                 stream) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (timed) {
-        (void)hipEventRecord(rec.e2, stream);
+        (void)hipEventRecord(rec.e3, stream);
         profiler().finish(rec);
     }
     return ROTSEQ_SUCCESS;
@@ -443,11 +485,15 @@ int rotseq_check_args(int64_t m, int64_t n, int64_t k, const void *A, int64_t ld
 size_t rotseq_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k, const rotseq_opts *opts)
 {
     int esize = dtype == 'd' ? 8 : dtype == 's' ? 4 : 0;
-    if (!esize || m <= 0 || n <= 1 || k <= 0)
+    if (!esize || k <= 0)
+        return 0;
+    const bool left = opts && opts->left;
+    if (left ? n <= 0 || m <= 1 : m <= 0 || n <= 1)
         return 0;
     Plan p;
-    const int64_t n1 = n - 1;
-    if (!plan_for(p, esize, m, n, k, m, n1, n1, opts))
+    size_t off_pack = 0;
+    const int64_t n1 = (left ? m : n) - 1;
+    if (!plan_for(p, esize, m, n, k, m, n1, n1, opts, kRotate, off_pack))
         return 0;
     return p.total;
 }
@@ -456,26 +502,40 @@ int rotseq_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const d
                 int64_t ldc, const double *S, int64_t lds, hipStream_t stream,
                 const rotseq_opts *opts, void *workspace, size_t ws_bytes)
 {
-    return run<double>(m, n, k, A, lda, C, ldc, S, lds, stream, opts, workspace, ws_bytes);
+    return run<double>(kRotate, m, n, k, A, lda, C, ldc, S, lds, stream, opts, workspace, ws_bytes);
 }
 
 int rotseq_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, const float *C,
                 int64_t ldc, const float *S, int64_t lds, hipStream_t stream,
                 const rotseq_opts *opts, void *workspace, size_t ws_bytes)
 {
-    return run<float>(m, n, k, A, lda, C, ldc, S, lds, stream, opts, workspace, ws_bytes);
+    return run<float>(kRotate, m, n, k, A, lda, C, ldc, S, lds, stream, opts, workspace, ws_bytes);
+}
+
+int rotseq_refl_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const double *TAU,
+                     int64_t ldt, const double *NU, int64_t ldn, hipStream_t stream,
+                     const rotseq_opts *opts, void *workspace, size_t ws_bytes)
+{
+    return run<double>(kReflect, m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace, ws_bytes);
+}
+
+int rotseq_refl_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, const float *TAU,
+                     int64_t ldt, const float *NU, int64_t ldn, hipStream_t stream,
+                     const rotseq_opts *opts, void *workspace, size_t ws_bytes)
+{
+    return run<float>(kReflect, m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace, ws_bytes);
 }
 
 int rotseq_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const double *C, int64_t ldc,
              const double *S, int64_t lds, hipStream_t stream)
 {
-    return run<double>(m, n, k, A, lda, C, ldc, S, lds, stream, nullptr, nullptr, 0);
+    return run<double>(kRotate, m, n, k, A, lda, C, ldc, S, lds, stream, nullptr, nullptr, 0);
 }
 
 int rotseq_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, const float *C, int64_t ldc,
              const float *S, int64_t lds, hipStream_t stream)
 {
-    return run<float>(m, n, k, A, lda, C, ldc, S, lds, stream, nullptr, nullptr, 0);
+    return run<float>(kRotate, m, n, k, A, lda, C, ldc, S, lds, stream, nullptr, nullptr, 0);
 }
 
 const char *rotseq_strerror(int code)

@@ -13,6 +13,11 @@ namespace rotseq {
 // Per-rotation arithmetic (values of rotseq_opts.arith after resolving AUTO).
 enum Arith : int { kExact = 1, kFma = 2, kLift = 3 };
 
+// What the (C, S) arrays of a call hold: rotations (c, s); 2x2 reflectors
+// (tau, nu); or reflectors read on the column-reversed matrix (the inverse
+// order of a reflector sequence).
+enum Kind : int { kRotate = 0, kReflect = 1, kReflectRev = 2 };
+
 // Sweep kernel families (values of rotseq_opts.kernel after resolving AUTO).
 enum Kernel : int { kMultipass = 1, kChain = 2 };
 
@@ -41,6 +46,7 @@ struct Plan {
     int pad;     // identity records after the last step of each band
     int unroll;  // kernel unroll length (register ring size)
     int arith;
+    int kind;    // Kind
     int esize;   // sizeof element: 8 (double) or 4 (float)
     // Launch shape of the chain kernel (configure_launch).
     int waves, nwg, remap, publish, spin_limit;
@@ -123,5 +129,9 @@ hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stre
 hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws,
                        hipStream_t stream);
 hipError_t launch_sweep(const Plan &p, void *A, const void *ws, hipStream_t stream);
+// dst (cols x rows, leading dimension ldd) = transpose of src (rows x cols,
+// leading dimension lds_src); both column-major, esize 8 or 4.
+hipError_t launch_transpose(const void *src, int64_t rows, int64_t cols, int64_t lds_src, void *dst,
+                            int64_t ldd, int esize, hipStream_t stream);
 
 }  // namespace rotseq

@@ -27,6 +27,8 @@
 // out-of-range stores are dropped by the hardware without a branch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rotseq_internal.h"
 
 namespace rotseq {
@@ -200,48 +202,94 @@ __global__ __launch_bounds__(kWave) void sweep_multipass(T *__restrict__ A, int6
 // ------------------------------------------------------------------ prep
 //
 // Column signs of the lifting form: a rotation with c < 0 is applied as
-// (-c, -s) and leaves both of its columns negated.  neg(j,p) = [C(j,p) < 0]
-// is known up front, so the sign of column j just before rotation (j,p) in
-// Algorithm 2's order is the parity of neg over the rotations that touched it
-// earlier: (j-1, p') for p' <= p and (j, p') for p' < p.  A rotation sees its
-// columns' signs only through their product, which turns s into
-// s' = s * sign(j) * sign(j+1).
+// (-c, -s) and leaves both of its columns negated.  A 2x2 reflector (kinds
+// kReflect, kReflectRev) is a rotation followed by negating its right
+// column, so it may negate either column alone.  Which columns pair (j,p)
+// negates is known up front: bit q of the low half of negmask for the left
+// column j, of the high half for the right column j+1.  The sign of a column
+// just before rotation (j,p) in Algorithm 2's order is the parity of the
+// negations by the rotations that touched it earlier:
+//   column j:   (j-1, p') as its right column for p' <= p,
+//               (j, p')   as its left column for p' < p;
+//   column j+1: (j, p')   as its right column for p' < p,
+//               (j+1, p') as its left column for p' < p.
+// A rotation sees its columns' signs only through their product, which turns
+// s into s' = s * sign(j) * sign(j+1).  For plain rotations both halves of
+// negmask are equal and the terms of pair j cancel.
 
 __device__ __forceinline__ uint64_t low_bits(int q) { return q >= 64 ? ~0ull : ((1ull << q) - 1); }
 
-// negmask[pass*(n-1) + j] bit q = [C(j, pass*K + q) < 0].
+// Rotation part (c, s) of pair (j, p) of a sequence kind, and whether the
+// pair also negates its right column.  Kind kReflect reads (C, S) as
+// (tau, nu): H = I - tau v v^T with v = (1, nu) acts on (x, y) as
+//   x' = (1-tau) x - tau nu y,   y' = -tau nu x + (1 - tau nu^2) y,
+// and for an orthogonal H (tau (1 + nu^2) = 2) the second row is
+// -(-s x + c y) with c = 1 - tau, s = -tau nu: the rotation (c, s), then the
+// right column negated (none of this for tau = 0, where H = I).  Kind
+// kReflectRev is the same reflector seen on the column-reversed matrix,
+// where its left and right columns trade places: the rotation (-c, s),
+// then the (new) right column negated (and still the identity for tau = 0).
+template <typename T>
+__device__ __forceinline__ void pair_rotation(int kind, T cv, T sv, double &c, double &s, bool &flip)
+{
+    if (kind == kRotate) {
+        c = (double)cv;
+        s = (double)sv;
+        flip = false;
+    } else {
+        const double tau = (double)cv, nu = (double)sv;
+        flip = tau != 0.0;
+        c = 1.0 - tau;
+        if (kind == kReflectRev && flip)
+            c = -c;
+        s = -(tau * nu);
+    }
+}
+
+// negmask[pass*(n-1) + j]: bit q = pair (j, pass*K + q) negates column j,
+// bit 32 + q = it negates column j+1 (K <= 32).
 template <typename T>
 __device__ __forceinline__ uint64_t negmask_elem(const T *__restrict__ C, int64_t cj, int64_t ldc,
-                                                 int64_t n1, int64_t k, int K, int64_t idx)
+                                                 const T *__restrict__ S, int64_t lds, int64_t n1,
+                                                 int64_t k, int K, int kind, int64_t idx)
 {
     const int64_t pass = idx / n1, j = idx - pass * n1;
     uint64_t mask = 0;
     for (int q = 0; q < K; ++q) {
         const int64_t p = pass * K + q;
-        if (p < k && C[j * cj + p * ldc] < T(0))
-            mask |= 1ull << q;
+        if (p >= k)
+            continue;
+        double c, s;
+        bool flip;
+        pair_rotation(kind, C[j * cj + p * ldc], kind == kRotate ? T(0) : S[j * cj + p * lds], c, s,
+                      flip);
+        const uint64_t neg = c < 0.0 ? 1u : 0u;
+        mask |= (neg << q) | ((neg ^ (flip ? 1u : 0u)) << (32 + q));
     }
     return mask;
 }
 
-// parity[pass*(n-1) + j] = parity of the negations by pair j in bands < pass,
-// for pass = 0 .. npass (the last row is the total).
+// parity[pass*(n-1) + j] = parities of the negations by pair j in bands
+// < pass (bit 0: of its left column, bit 1: of its right column), for
+// pass = 0 .. npass (the last row is the total).
 __device__ __forceinline__ void parity_elem(const uint64_t *__restrict__ negmask, int64_t n1,
                                             int npass, uint8_t *__restrict__ parity, int64_t j)
 {
     unsigned acc = 0;
     for (int pass = 0; pass < npass; ++pass) {
         parity[(int64_t)pass * n1 + j] = (uint8_t)acc;
-        acc ^= __builtin_popcountll(negmask[(int64_t)pass * n1 + j]) & 1u;
+        const uint64_t nm = negmask[(int64_t)pass * n1 + j];
+        acc ^= (__builtin_popcount((unsigned)nm) & 1u) | ((__builtin_popcount((unsigned)(nm >> 32)) & 1u) << 1);
     }
     parity[(int64_t)npass * n1 + j] = (uint8_t)acc;
 }
 
-// sign[c] = (-1)^(negations of column c by pairs c-1 and c over all bands).
+// sign[c] = (-1)^(negations of column c: as the right column of pair c-1 and
+// the left column of pair c, over all bands).
 template <typename T>
 __device__ __forceinline__ T sign_elem(const uint8_t *__restrict__ total, int64_t n, int64_t c)
 {
-    const unsigned f = (c > 0 ? total[c - 1] : 0u) ^ (c + 1 < n ? total[c] : 0u);
+    const unsigned f = ((c > 0 ? total[c - 1] >> 1 : 0u) ^ (c + 1 < n ? total[c] : 0u)) & 1u;
     return f ? T(-1) : T(1);
 }
 
@@ -252,7 +300,7 @@ template <typename T>
 __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_t cj, int64_t ldc,
                                                  const T *__restrict__ S, int64_t lds, int64_t n1,
                                                  int64_t k, int K, int steps, int pad, int arith,
-                                                 const uint64_t *__restrict__ negmask,
+                                                 int kind, const uint64_t *__restrict__ negmask,
                                                  const uint8_t *__restrict__ parity, int64_t idx)
 {
     const int q = (int)(idx % K);
@@ -265,13 +313,20 @@ __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_
         if (arith == kLift) {
             const uint64_t *nm = negmask + pass * n1;
             const uint8_t *par = parity + pass * n1;
+            const uint64_t lo = low_bits(q), lo1 = low_bits(q + 1);
+            // sign(j) * sign(j+1) as a parity (see the comment above low_bits)
             unsigned tau = 0;
             if (j > 0)
-                tau ^= par[j - 1] ^ (__builtin_popcountll(nm[j - 1] & low_bits(q + 1)) & 1u);
+                tau ^= (par[j - 1] >> 1) ^ (__builtin_popcountll((nm[j - 1] >> 32) & lo1) & 1u);
+            tau ^= par[j] ^ (par[j] >> 1) ^ (__builtin_popcountll((nm[j] & lo) ^ ((nm[j] >> 32) & lo)) & 1u);
             if (j + 1 < n1)
-                tau ^= par[j + 1] ^ (__builtin_popcountll(nm[j + 1] & low_bits(q)) & 1u);
-            const double cd = (double)c;
-            const double sd = tau ? -(double)s : (double)s;
+                tau ^= par[j + 1] ^ (__builtin_popcountll(nm[j + 1] & lo) & 1u);
+            tau &= 1u;
+            double cd, sr;
+            bool flip;
+            pair_rotation(kind, c, s, cd, sr, flip);
+            (void)flip;  // the negation is in negmask
+            const double sd = tau ? -sr : sr;
             double a, b;
             if (!(cd < 0.0)) {
                 a = sd / (1.0 + cd);
@@ -294,13 +349,14 @@ __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_
 }
 
 template <typename T>
-__global__ void prep_negmask(const T *__restrict__ C, int64_t cj, int64_t ldc, int64_t n1, int64_t k,
-                             int K, int npass, uint64_t *__restrict__ negmask)
+__global__ void prep_negmask(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
+                             int64_t lds, int64_t n1, int64_t k, int K, int npass, int kind,
+                             uint64_t *__restrict__ negmask)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)npass * n1)
         return;
-    negmask[idx] = negmask_elem(C, cj, ldc, n1, k, K, idx);
+    negmask[idx] = negmask_elem(C, cj, ldc, S, lds, n1, k, K, kind, idx);
 }
 
 __global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
@@ -324,14 +380,14 @@ __global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__res
 template <typename T>
 __global__ void prep_coef(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
                           int64_t lds, int64_t n1, int64_t k, int K, int steps, int pad, int npass,
-                          int arith, const uint64_t *__restrict__ negmask,
+                          int arith, int kind, const uint64_t *__restrict__ negmask,
                           const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)npass * (steps + pad) * K;
     if (idx >= total)
         return;
-    coef[idx] = coef_elem(C, cj, ldc, S, lds, n1, k, K, steps, pad, arith, negmask, parity, idx);
+    coef[idx] = coef_elem(C, cj, ldc, S, lds, n1, k, K, steps, pad, arith, kind, negmask, parity, idx);
 }
 
 __global__ void prep_zero(int *__restrict__ p, int64_t count)
@@ -339,6 +395,49 @@ __global__ void prep_zero(int *__restrict__ p, int64_t count)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count)
         p[i] = 0;
+}
+
+// ------------------------------------------------------------- packing
+//
+// Left application packs A transposed (Section 4.3: a packed copy laid out
+// the way the sweep reads it), so the rows the rotations mix become the
+// contiguous columns the sweep streams.  One 256-thread workgroup moves a
+// 64 x 64 tile through LDS: it reads 64-element column segments of the
+// source (512 B for FP64, one per wave and instruction) and writes 64-element
+// column segments of the destination, so both sides are coalesced.  The tile
+// has one padding column, which spreads a transposed read of LDS over all
+// banks.
+
+constexpr int kTile = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_tiles(const T *__restrict__ src, int64_t rows,
+                                                       int64_t cols, int64_t lds_src,
+                                                       T *__restrict__ dst, int64_t ldd,
+                                                       int64_t tiles_r, int64_t ntiles)
+{
+    __shared__ T tile[kTile][kTile + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
+        const int64_t r0 = (tid % tiles_r) * kTile, c0 = (tid / tiles_r) * kTile;
+        const int64_t r = r0 + lane;
+#pragma unroll 4
+        for (int cc = wave; cc < kTile; cc += 4) {
+            const int64_t c = c0 + cc;
+            if (r < rows && c < cols)
+                tile[cc][lane] = src[r + c * lds_src];
+        }
+        __syncthreads();
+        // dst(c, r) = src(r, c): destination column r holds source row r.
+        const int64_t c = c0 + lane;
+#pragma unroll 4
+        for (int rr = wave; rr < kTile; rr += 4) {
+            const int64_t rw = r0 + rr;
+            if (rw < rows && c < cols)
+                dst[c + rw * ldd] = tile[lane][rr];
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------ batched prep
@@ -390,14 +489,15 @@ __global__ void prep_batch(const BatchItem *__restrict__ items, int count, int64
     const int64_t i = idx - stage_off<STAGE>(it);
     const int64_t n1 = it.n - 1;
     if constexpr (STAGE == kStageNegmask)
-        it.negmask[i] = negmask_elem((const T *)it.C, 1, it.ldc, n1, it.k, K, i);
+        it.negmask[i] = negmask_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1, it.k, K,
+                                     kRotate, i);
     else if constexpr (STAGE == kStageParity)
         parity_elem(it.negmask, n1, it.npass, it.parity, i);
     else if constexpr (STAGE == kStageSign)
         ((T *)it.sign)[i] = sign_elem<T>(it.parity + (int64_t)it.npass * n1, it.n, i);
     else if constexpr (STAGE == kStageCoef)
         ((CoefPair<T> *)it.coef)[i] = coef_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1,
-                                                it.k, K, it.steps, it.pad, arith, it.negmask,
+                                                it.k, K, it.steps, it.pad, arith, kRotate, it.negmask,
                                                 it.parity, i);
     else
         it.flags[i] = 0;
@@ -415,8 +515,8 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
     CoefPair<T> *coef = (CoefPair<T> *)(ws + p.off_coef);
     constexpr int B = 256;
     if (p.arith == kLift) {
-        prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(C, p.cstep, p.ldc, n1, p.k,
-                                                                          p.band, p.npass, negmask);
+        prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(
+            C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band, p.npass, p.kind, negmask);
         prep_parity<<<blocks_for(n1, B), B, 0, st>>>(negmask, n1, p.npass, parity);
         prep_sign<T><<<blocks_for(p.n, B), B, 0, st>>>(parity + (int64_t)p.npass * n1, p.n, sign);
     }
@@ -426,8 +526,8 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
         prep_zero<<<blocks_for(words, B), B, 0, st>>>((int *)(ws + p.off_flags), words);
     }
     prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band,
-                                                    p.steps, p.pad, p.npass, p.arith, negmask, parity,
-                                                    coef);
+                                                    p.steps, p.pad, p.npass, p.arith, p.kind, negmask,
+                                                    parity, coef);
     return hipGetLastError();
 }
 
@@ -498,6 +598,23 @@ hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws, hi
     if (p.esize == 8)
         return prep_t<double>(p, (const double *)C, (const double *)S, (char *)ws, stream);
     return prep_t<float>(p, (const float *)C, (const float *)S, (char *)ws, stream);
+}
+
+hipError_t launch_transpose(const void *src, int64_t rows, int64_t cols, int64_t lds_src, void *dst,
+                            int64_t ldd, int esize, hipStream_t stream)
+{
+    if (rows <= 0 || cols <= 0)
+        return hipSuccess;
+    const int64_t tiles_r = (rows + kTile - 1) / kTile;
+    const int64_t ntiles = tiles_r * ((cols + kTile - 1) / kTile);
+    const unsigned grid = (unsigned)std::min<int64_t>(ntiles, (int64_t)1 << 20);
+    if (esize == 8)
+        transpose_tiles<double><<<grid, 256, 0, stream>>>((const double *)src, rows, cols, lds_src,
+                                                          (double *)dst, ldd, tiles_r, ntiles);
+    else
+        transpose_tiles<float><<<grid, 256, 0, stream>>>((const float *)src, rows, cols, lds_src,
+                                                         (float *)dst, ldd, tiles_r, ntiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_prep_batch(const BatchLaunch &b, hipStream_t stream)

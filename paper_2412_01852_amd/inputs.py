@@ -12,6 +12,9 @@ below restate the workloads this library is measured on:
 
 Generators are numpy PCG64 seeded per problem; batches of problems use
 independent streams from ``SeedSequence(seed).spawn(count)``.
+
+Reflector sequences (the paper's 2x2 reflector variant) and rotations that
+mix rows get their own generators with the same conventions.
 """
 from dataclasses import dataclass
 import math
@@ -57,6 +60,49 @@ def make_problem(m, n, k, seed=0, *, lda=None, ldc=None, lds=None,
     C[...] = np.cos(theta)
     S[...] = np.sin(theta)
     return Problem(m, n, k, A, C, S)
+
+
+def make_left_problem(m, n, k, seed=0, *, lda=None, ldc=None, lds=None, pad_fill=np.nan):
+    """Problem for rotations that mix rows: A is m x n, C and S are (m-1) x k
+    (same distributions as make_problem; ``Problem.C`` keeps the (m-1) rows)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    _, A = _colmajor_buffer(m, n, lda, pad_fill)
+    A[...] = rng.standard_normal(m * n).reshape(n, m).T
+    mm1 = max(m - 1, 0)
+    theta = rng.uniform(0.0, TWO_PI, mm1 * k).reshape(k, mm1).T
+    _, C = _colmajor_buffer(mm1, k, ldc, pad_fill)
+    _, S = _colmajor_buffer(mm1, k, lds, pad_fill)
+    C[...] = np.cos(theta)
+    S[...] = np.sin(theta)
+    return Problem(m, n, k, A, C, S)
+
+
+def make_reflectors(r, k, rng, *, ld_tau=None, ld_nu=None, identity_frac=0.05,
+                    pad_fill=np.nan):
+    """(r x k) reflector parameters (tau, nu) of orthogonal 2x2 reflectors
+    I - tau v v^T, v = (1, nu): nu = tan(phi) with phi uniform on
+    (-pi/2, pi/2), tau = 2 / (1 + nu^2) (so every angle of the reflecting
+    line is equally likely), and a fraction ``identity_frac`` of tau = 0
+    (identity) entries as an annihilation of an already-zero entry gives."""
+    phi = rng.uniform(-0.5 * math.pi, 0.5 * math.pi, r * k).reshape(k, r).T
+    ident = rng.uniform(0.0, 1.0, r * k).reshape(k, r).T < identity_frac
+    _, TAU = _colmajor_buffer(r, k, ld_tau, pad_fill)
+    _, NU = _colmajor_buffer(r, k, ld_nu, pad_fill)
+    NU[...] = np.tan(phi)
+    TAU[...] = np.where(ident, 0.0, 2.0 / (1.0 + NU * NU))
+    return TAU, NU
+
+
+def make_refl_problem(m, n, k, seed=0, *, left=False, lda=None, ldc=None, lds=None,
+                      pad_fill=np.nan):
+    """Reflector problem: A i.i.d. normal (m x n); ``Problem.C`` holds tau and
+    ``Problem.S`` holds nu, (n-1) x k, or (m-1) x k with ``left``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    _, A = _colmajor_buffer(m, n, lda, pad_fill)
+    A[...] = rng.standard_normal(m * n).reshape(n, m).T
+    r = max((m if left else n) - 1, 0)
+    TAU, NU = make_reflectors(r, k, rng, ld_tau=ldc, ld_nu=lds, pad_fill=pad_fill)
+    return Problem(m, n, k, A, TAU, NU)
 
 
 def make_cs(n, k, rng):

@@ -25,27 +25,53 @@ def plan(n, k, band=0):
     return band, npass, steps, unroll
 
 
-def prep(C, S, band, npass, steps, arith):
-    """Coefficient records coef[pass, t, q] = (a, b) and final column signs."""
+def pair_rotation(kind, cv, sv):
+    """(c, s, flip): the rotation part of a pair and whether it then negates
+    its right column.  kind "rotate": (C, S) = (c, s).  "reflect": (C, S) =
+    (tau, nu) of H = I - tau v v^T, v = (1, nu), which for an orthogonal H is
+    the rotation (1 - tau, -tau nu) followed by negating the right column
+    (nothing for tau = 0).  "reflect_rev": the same reflector on the
+    column-reversed matrix, the rotation (tau - 1, -tau nu) then the flip
+    (still the identity for tau = 0)."""
+    if kind == "rotate":
+        return cv, sv, False
+    flip = cv != 0.0
+    c = 1.0 - cv
+    if kind == "reflect_rev" and flip:  # tau = 0 is the identity either way
+        c = -c
+    return c, -(cv * sv), flip
+
+
+def prep(C, S, band, npass, steps, arith, kind="rotate"):
+    """Coefficient records coef[pass, t, q] = (a, b) and final column signs.
+
+    negL/negR[pass, j] bit q: pair (j, pass*band + q) negates its left/right
+    column (both for a rotation with c < 0; a reflector's flip toggles the
+    right one)."""
     n1, k = C.shape
     n = n1 + 1
-    neg = np.zeros((npass, n1), dtype=np.uint64)
+    negL = np.zeros((npass, n1), dtype=np.int64)
+    negR = np.zeros((npass, n1), dtype=np.int64)
     for pss in range(npass):
         for q in range(band):
             p = pss * band + q
-            if p < k:
-                neg[pss] |= (C[:, p] < 0).astype(np.uint64) << np.uint64(q)
-    par = np.zeros((npass + 1, n1), dtype=np.uint8)
-    acc = np.zeros(n1, dtype=np.uint8)
-    popc = np.vectorize(lambda v: bin(int(v)).count("1") & 1, otypes=[np.uint8])
+            if p >= k:
+                continue
+            for j in range(n1):
+                c, _, flip = pair_rotation(kind, C[j, p], S[j, p])
+                neg = 1 if c < 0 else 0
+                negL[pss, j] |= neg << q
+                negR[pss, j] |= (neg ^ int(flip)) << q
+    pc = lambda v: bin(int(v)).count("1") & 1  # noqa: E731
+    parL = np.zeros((npass + 1, n1), dtype=np.int64)
+    parR = np.zeros((npass + 1, n1), dtype=np.int64)
     for pss in range(npass):
-        par[pss] = acc
-        acc = acc ^ popc(neg[pss]) if n1 else acc
-    par[npass] = acc
-    tot = par[npass]
+        for j in range(n1):
+            parL[pss + 1, j] = parL[pss, j] ^ pc(negL[pss, j])
+            parR[pss + 1, j] = parR[pss, j] ^ pc(negR[pss, j])
     sign = np.ones(n)
     for c in range(n):
-        f = (int(tot[c - 1]) if c > 0 else 0) ^ (int(tot[c]) if c + 1 < n else 0)
+        f = (int(parR[npass, c - 1]) if c > 0 else 0) ^ (int(parL[npass, c]) if c + 1 < n else 0)
         sign[c] = -1.0 if f else 1.0
     coef = np.zeros((npass, steps, band, 2))
     low = lambda q: (1 << q) - 1  # noqa: E731
@@ -54,13 +80,18 @@ def prep(C, S, band, npass, steps, arith):
             for q in range(band):
                 j, p = t - q, pss * band + q
                 if 0 <= j < n1 and p < k:
-                    c, s = C[j, p], S[j, p]
+                    c, s, _ = pair_rotation(kind, C[j, p], S[j, p])
                     if arith == "lift":
-                        tau = 0
+                        # sign(j) before (j, p): (j-1, p' <= p) as right column,
+                        # (j, p' < p) as left column; sign(j+1): (j, p' < p) as
+                        # right column, (j+1, p' < p) as left column.
+                        sj = int(parL[pss, j]) ^ pc(negL[pss, j] & low(q))
                         if j > 0:
-                            tau ^= int(par[pss, j - 1]) ^ (bin(int(neg[pss, j - 1]) & low(q + 1)).count("1") & 1)
+                            sj ^= int(parR[pss, j - 1]) ^ pc(negR[pss, j - 1] & low(q + 1))
+                        sj1 = int(parR[pss, j]) ^ pc(negR[pss, j] & low(q))
                         if j + 1 < n1:
-                            tau ^= int(par[pss, j + 1]) ^ (bin(int(neg[pss, j + 1]) & low(q)).count("1") & 1)
+                            sj1 ^= int(parL[pss, j + 1]) ^ pc(negL[pss, j + 1] & low(q))
+                        tau = sj ^ sj1
                         sd = -s if tau else s
                         if not (c < 0):
                             a, b = sd / (1.0 + c), -sd
@@ -84,14 +115,16 @@ def rotate(x, y, a, b, arith):
     return x, y
 
 
-def sweep(A, C, S, band=0, arith="exact"):
-    """Apply the rotations to the (m, n) float64 array A in kernel order."""
+def sweep(A, C, S, band=0, arith="exact", kind="rotate"):
+    """Apply the rotations (or, with kind "reflect"/"reflect_rev", the
+    reflectors (C, S) = (tau, nu)) to the (m, n) float64 array A in kernel
+    order."""
     m, n = A.shape
     k = C.shape[1]
     if m == 0 or n <= 1 or k == 0:
         return A
     K, npass, steps, R = plan(n, k, band)
-    coef, sign = prep(C, S, K, npass, steps, arith)
+    coef, sign = prep(C, S, K, npass, steps, arith, kind)
     D = PREFETCH
     col = lambda c: A[:, c].copy() if 0 <= c < n else np.zeros(m)  # noqa: E731
     for pss in range(npass):

@@ -153,6 +153,48 @@ def test_new_error_codes_have_descriptions():
 
 def test_options_struct_layout():
     """rotseq_opts is eight int32 fields: arith, kernel, band, waves, publish,
-    inverse, reserved[2]."""
+    inverse, left, reserved."""
     assert ctypes.sizeof(rs.Options) == 32
     assert rs.Options.inverse.offset == 20
+    assert rs.Options.left.offset == 24
+
+
+def _ex(fn, m, n, k, A, lda, C, ldc, S, lds, opts=None):
+    lib = rs._lib._load()
+    o = rs._lib._opts(opts)
+    return getattr(lib, fn)(m, n, k, A, lda, C, ldc, S, lds, None, o, None, 0)
+
+
+@pytest.mark.parametrize("fn", ["rotseq_ex_d", "rotseq_refl_ex_d", "rotseq_refl_ex_s"])
+def test_left_argument_checks_without_device(fn):
+    """With left application C/S (or TAU/NU) have m-1 rows and the work
+    condition is n > 0, m > 1; all checked before any device call."""
+    L = {"left": 1}
+    assert _ex(fn, 6, 3, 2, 1, 6, 1, 2, 1, 5, L) == -7   # ldc = n-1 is too small for left
+    assert _ex(fn, 6, 3, 2, 1, 6, 1, 5, 1, 4, L) == -9
+    assert _ex(fn, 6, 3, 2, 1, 5, 1, 5, 1, 5, L) == -5   # lda >= m still
+    assert _ex(fn, 6, 3, 2, None, 6, 1, 5, 1, 5, L) == -4
+    assert _ex(fn, 6, 0, 2, None, 6, None, 5, None, 5, L) == 0  # n == 0: quick return
+    assert _ex(fn, 1, 7, 2, None, 1, None, 1, None, 1, L) == 0  # m == 1: quick return
+    # the same shape without `left` checks C against n-1
+    assert _ex(fn, 6, 3, 2, 1, 6, 1, 1, 1, 2) == -7
+
+
+def test_reflectors_need_lifting():
+    """Reflectors run only in the lifting form; other arithmetic is refused
+    before anything touches the device."""
+    for arith in (rs.ARITH_EXACT, rs.ARITH_FMA):
+        assert _ex("rotseq_refl_ex_d", 64, 10, 3, 1, 64, 1, 9, 1, 9, {"arith": arith}) == 4
+
+
+def test_left_workspace_adds_packed_copy():
+    """Left application sweeps the transposed n x m copy packed into the
+    workspace after the plan's own buffers."""
+    m, n, k = 300, 70, 16
+    left = rs.workspace_bytes("float64", m, n, k, {"left": 1})
+    right_t = rs.workspace_bytes("float64", n, m, k)
+    assert left >= right_t + m * n * 8
+    assert left - (right_t + m * n * 8) < 256
+    assert rs.workspace_bytes("float64", 1, 70, 16, {"left": 1}) == 0
+    assert rs.workspace_bytes("float64", 300, 0, 16, {"left": 1}) == 0
+    assert rs.workspace_bytes("float64", 300, 1, 16, {"left": 1}) > 0

@@ -1,0 +1,234 @@
+"""GPU parity of left application (rotations mixing rows, `opts.left`) and of
+2x2 reflector sequences (rotseq_refl_ex_*) through the C ABI, against the CPU
+oracle's own loops for them: bitwise in exact mode where the arithmetic is the
+oracle's, within the FP64/FP32 tolerances otherwise; ragged shapes and padded
+leading dimensions, both kernels, the inverse order, a row-major matrix, and
+the 10240^2, k = 192 size on sampled rows or columns.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2412_01852_amd as rs
+from paper_2412_01852_amd.inputs import make_left_problem, make_refl_problem
+from gpu_util import TOL, padding_bits, relerr, say, to_dev, widened
+
+pytestmark = pytest.mark.gpu
+
+ARITHS = {"exact": rs.ARITH_EXACT, "fma": rs.ARITH_FMA, "lift": rs.ARITH_LIFT}
+KERNELS = {"chain": rs.KERNEL_CHAIN, "multipass": rs.KERNEL_MULTIPASS}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def _sync_ok():
+    import torch
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+
+
+# m x n, k, padding of lda / ldc / lds: ragged row tiles of the packed A^T
+# (n not a multiple of 64), m = 2 (one rotation per sequence), k > m,
+# k not a multiple of the band, a single column.
+LEFT_SHAPES = [(130, 17, 33, 1, 0, 2), (64, 64, 64, 0, 0, 0), (2, 100, 5, 0, 1, 0),
+               (200, 3, 9, 3, 0, 0), (257, 129, 16, 0, 2, 1), (9, 1, 12, 0, 0, 0),
+               (1000, 70, 24, 5, 0, 0)]
+
+
+def _oracle_left(pb, dtype, inverse=False):
+    ref = oracle.colmajor(widened(pb.A, dtype))
+    oracle.rotseq(ref, oracle.colmajor(widened(pb.C, dtype)), oracle.colmajor(widened(pb.S, dtype)),
+                  left=True, inverse=inverse)
+    return np.asarray(ref)
+
+
+@pytest.mark.parametrize("m,n,k,pa,pc,ps", LEFT_SHAPES)
+@pytest.mark.parametrize("arith", ["exact", "lift"])
+@pytest.mark.parametrize("kernel", ["chain", "multipass"])
+def test_left_fp64(m, n, k, pa, pc, ps, arith, kernel):
+    say(f"left fp64 m={m} n={n} k={k} arith={arith} kernel={kernel}")
+    pb = make_left_problem(m, n, k, seed=7 * m + n + k, lda=m + pa, ldc=m - 1 + pc, lds=m - 1 + ps)
+    A = to_dev(pb.A, "f64")
+    C, S = to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    pad_before = padding_bits(A)
+    opts = {"arith": ARITHS[arith], "kernel": KERNELS[kernel], "left": 1}
+    rs.rotseq(A, C, S, opts=opts)
+    _sync_ok()
+    assert np.array_equal(pad_before, padding_bits(A)), "padding rows of A were modified"
+    got, ref = rs.host_colmajor(A), _oracle_left(pb, "f64")
+    if arith == "exact":
+        assert np.array_equal(got, ref), "exact left application must equal the oracle's loop bitwise"
+    else:
+        assert relerr(got, ref, pb.A) <= TOL["f64"]
+    # the inverse (A <- Q A) against the oracle, then as the undo of the forward call
+    rs.rotseq(A, C, S, opts=dict(opts, inverse=1))
+    _sync_ok()
+    assert relerr(rs.host_colmajor(A), np.asarray(pb.A), pb.A) <= 2 * TOL["f64"]
+    B = to_dev(pb.A, "f64")
+    rs.rotseq(B, C, S, opts=dict(opts, inverse=1))
+    _sync_ok()
+    refi = _oracle_left(pb, "f64", inverse=True)
+    if arith == "exact":
+        assert np.array_equal(rs.host_colmajor(B), refi)
+    else:
+        assert relerr(rs.host_colmajor(B), refi, pb.A) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("m,n,k", [(130, 17, 33), (257, 129, 16), (64, 300, 8)])
+def test_left_fp32(m, n, k):
+    say(f"left fp32 m={m} n={n} k={k}")
+    pb = make_left_problem(m, n, k, seed=11 + m)
+    A = to_dev(pb.A, "f32")
+    rs.rotseq(A, to_dev(pb.C, "f32"), to_dev(pb.S, "f32"), opts={"left": 1})
+    _sync_ok()
+    assert relerr(rs.host_colmajor(A), _oracle_left(pb, "f32"), widened(pb.A, "f32")) <= TOL["f32"]
+
+
+def test_left_caller_workspace():
+    """With a caller workspace of rotseq_workspace_bytes (packed copy
+    included) the call allocates nothing and gives the cached-pool result."""
+    import torch
+    say("left with a caller workspace")
+    pb = make_left_problem(300, 77, 20, seed=5)
+    opts = {"left": 1, "arith": rs.ARITH_EXACT}
+    nbytes = rs.workspace_bytes("float64", 300, 77, 20, opts)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    A = to_dev(pb.A, "f64")
+    rs.rotseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"), opts=opts, workspace=ws)
+    _sync_ok()
+    assert np.array_equal(rs.host_colmajor(A), _oracle_left(pb, "f64"))
+
+
+def test_row_major_right_application():
+    """Right application to a row-major r x q matrix B is the left application
+    to the column-major q x r matrix in the same memory: bitwise equal to the
+    oracle's right application on B in exact mode."""
+    import torch
+    say("row-major right application")
+    r, q, k = 150, 41, 13
+    rng = np.random.Generator(np.random.PCG64(21))
+    B = rng.standard_normal((r, q))
+    th = rng.uniform(0, 2 * np.pi, (q - 1, k))
+    Bd = torch.from_numpy(B.copy()).cuda()  # row-major: element (i, j) at i*q + j
+    view = Bd.t()                            # q x r column-major view, leading dimension q
+    C = to_dev(np.asfortranarray(np.cos(th)), "f64")
+    S = to_dev(np.asfortranarray(np.sin(th)), "f64")
+    rs.rotseq(view, C, S, opts={"left": 1, "arith": rs.ARITH_EXACT})
+    _sync_ok()
+    ref = oracle.colmajor(B)
+    oracle.rotseq(ref, oracle.colmajor(np.cos(th)), oracle.colmajor(np.sin(th)))
+    assert np.array_equal(Bd.cpu().numpy(), np.asarray(ref))
+
+
+def test_left_target_sampled_columns():
+    """Left application at 10240^2, k = 192 (the packed copy is 0.84 GB):
+    columns are independent, so the oracle runs on a sample of them."""
+    say("left 10240^2 k=192 sampled columns")
+    pb = make_left_problem(10240, 10240, 192, seed=2)
+    A = to_dev(pb.A, "f64")
+    rs.rotseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"), opts={"left": 1})
+    _sync_ok()
+    cols = np.array([0, 1, 63, 64, 5000, 10238, 10239])
+    sub = oracle.colmajor(np.asarray(pb.A)[:, cols])
+    oracle.rotseq(sub, oracle.colmajor(pb.C), oracle.colmajor(pb.S), left=True)
+    got = rs.host_colmajor(A)[:, cols]
+    assert relerr(got, np.asarray(sub), np.asarray(pb.A)[:, cols]) <= TOL["f64"]
+
+
+# ------------------------------------------------------------- reflectors
+
+REFL_SHAPES = [(130, 17, 33, 2, 1, 0), (64, 64, 64, 0, 0, 0), (1, 2, 1, 0, 0, 0),
+               (200, 2, 9, 1, 0, 3), (3, 129, 128, 1, 0, 0), (257, 300, 16, 3, 2, 1)]
+
+
+def _oracle_refl(pb, dtype, inverse=False, left=False):
+    ref = oracle.colmajor(widened(pb.A, dtype))
+    oracle.reflseq(ref, oracle.colmajor(widened(pb.C, dtype)), oracle.colmajor(widened(pb.S, dtype)),
+                   inverse=inverse, left=left)
+    return np.asarray(ref)
+
+
+@pytest.mark.parametrize("m,n,k,pa,pc,ps", REFL_SHAPES)
+@pytest.mark.parametrize("kernel", ["chain", "multipass"])
+def test_refl_fp64(m, n, k, pa, pc, ps, kernel):
+    say(f"reflectors fp64 m={m} n={n} k={k} kernel={kernel}")
+    pb = make_refl_problem(m, n, k, seed=13 * m + n + k, lda=m + pa, ldc=n - 1 + pc, lds=n - 1 + ps)
+    A = to_dev(pb.A, "f64")
+    TAU, NU = to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    pad_before = padding_bits(A)
+    opts = {"kernel": KERNELS[kernel]}
+    rs.reflseq(A, TAU, NU, opts=opts)
+    _sync_ok()
+    assert np.array_equal(pad_before, padding_bits(A)), "padding rows of A were modified"
+    assert relerr(rs.host_colmajor(A), _oracle_refl(pb, "f64"), pb.A) <= TOL["f64"]
+    # reverse order: undoes the forward call, and matches the oracle's reverse loop
+    rs.reflseq(A, TAU, NU, opts=dict(opts, inverse=1))
+    _sync_ok()
+    assert relerr(rs.host_colmajor(A), np.asarray(pb.A), pb.A) <= 2 * TOL["f64"]
+    B = to_dev(pb.A, "f64")
+    rs.reflseq(B, TAU, NU, opts=dict(opts, inverse=1))
+    _sync_ok()
+    assert relerr(rs.host_colmajor(B), _oracle_refl(pb, "f64", inverse=True), pb.A) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("m,n,k", [(130, 17, 33), (300, 257, 16)])
+def test_refl_left_fp64(m, n, k):
+    say(f"reflectors from the left fp64 m={m} n={n} k={k}")
+    pb = make_refl_problem(m, n, k, seed=3 + m, left=True)
+    A = to_dev(pb.A, "f64")
+    rs.reflseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"), opts={"left": 1})
+    _sync_ok()
+    assert relerr(rs.host_colmajor(A), _oracle_refl(pb, "f64", left=True), pb.A) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("m,n,k", [(130, 17, 33), (257, 300, 16)])
+def test_refl_fp32(m, n, k):
+    say(f"reflectors fp32 m={m} n={n} k={k}")
+    pb = make_refl_problem(m, n, k, seed=17 + n)
+    A = to_dev(pb.A, "f32")
+    rs.reflseq(A, to_dev(pb.C, "f32"), to_dev(pb.S, "f32"))
+    _sync_ok()
+    assert relerr(rs.host_colmajor(A), _oracle_refl(pb, "f32"), widened(pb.A, "f32")) <= TOL["f32"]
+
+
+def test_refl_closed_forms():
+    """tau = 0 everywhere leaves A unchanged bitwise; (tau, nu) = (2, 0) is
+    diag(-1, 1) on every pair, so k sequences multiply columns 0..n-2 by
+    (-1)^k exactly."""
+    say("reflector closed forms")
+    rng = np.random.Generator(np.random.PCG64(31))
+    m, n, k = 100, 37, 5
+    A0 = rng.standard_normal((m, n))
+    A = to_dev(oracle.colmajor(A0), "f64")
+    rs.reflseq(A, to_dev(oracle.colmajor(np.zeros((n - 1, k))), "f64"),
+               to_dev(oracle.colmajor(rng.standard_normal((n - 1, k))), "f64"))
+    _sync_ok()
+    assert np.array_equal(rs.host_colmajor(A), A0)
+    A = to_dev(oracle.colmajor(A0), "f64")
+    rs.reflseq(A, to_dev(oracle.colmajor(np.full((n - 1, k), 2.0)), "f64"),
+               to_dev(oracle.colmajor(np.zeros((n - 1, k))), "f64"))
+    _sync_ok()
+    ref = A0.copy()
+    ref[:, :-1] *= (-1.0) ** k
+    assert np.array_equal(rs.host_colmajor(A), ref)
+
+
+def test_refl_target_sampled_rows():
+    """Reflectors at 10240^2, k = 192 in the default launch shape, sampled rows."""
+    say("reflectors 10240^2 k=192 sampled rows")
+    pb = make_refl_problem(10240, 10240, 192, seed=2)
+    A = to_dev(pb.A, "f64")
+    rs.reflseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"))
+    _sync_ok()
+    rows = np.array([0, 1, 63, 64, 5000, 10238, 10239])
+    sub = oracle.colmajor(np.asarray(pb.A)[rows])
+    oracle.reflseq(sub, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
+    got = rs.host_colmajor(A)[rows]
+    assert relerr(got, np.asarray(sub), np.asarray(pb.A)[rows]) <= TOL["f64"]

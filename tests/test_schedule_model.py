@@ -44,3 +44,26 @@ def test_lifting_all_negative_cosines():
     oracle.rotseq(ref, C, S)
     got = sweep(np.array(A), np.asarray(C), np.asarray(S), band=4, arith="lift")
     assert np.linalg.norm(got - np.asarray(ref)) / np.linalg.norm(np.asarray(A)) < 1e-13
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES)
+@pytest.mark.parametrize("band", [1, 4, 8])
+def test_reflector_sign_bookkeeping(m, n, k, band):
+    """Reflectors as rotations plus tracked right-column negations (the
+    device's prep for rotseq_refl_ex_*) give the oracle's reflector loop; the
+    column-reversed reading gives its reverse loop."""
+    from paper_2412_01852_amd.inputs import make_reflectors
+    rng = np.random.Generator(np.random.PCG64(m * 5 + n * 11 + k))
+    A0 = rng.standard_normal((m, n))
+    tau, nu = make_reflectors(n - 1, k, rng, identity_frac=0.2)
+    tau, nu = np.array(tau), np.array(nu)
+    ref = colmajor(A0)
+    oracle.reflseq(ref, colmajor(tau), colmajor(nu))
+    got = sweep(A0.copy(), tau, nu, band=band, arith="lift", kind="reflect")
+    assert np.linalg.norm(got - np.asarray(ref)) / np.linalg.norm(A0) < 1e-13
+    # reverse order: the forward sweep on A[:, ::-1] with C/S read backwards
+    ref = colmajor(A0)
+    oracle.reflseq(ref, colmajor(tau), colmajor(nu), inverse=True)
+    got = sweep(A0[:, ::-1].copy(), tau[::-1, ::-1].copy(), nu[::-1, ::-1].copy(), band=band,
+                arith="lift", kind="reflect_rev")[:, ::-1]
+    assert np.linalg.norm(got - np.asarray(ref)) / np.linalg.norm(A0) < 1e-13
