@@ -36,6 +36,10 @@ WORKLOADS = {
        for k in (1, 8, 32, 128)},
     **{f"tall-f32-32768x4096-k{k}": dict(m=32768, n=4096, k=k, dtype="f32", seed=3 + k)
        for k in (1, 8, 32, 128)},
+    # rotations mixing rows (packed transposed copy around the same sweep)
+    "left-f64-10240-k192": dict(m=10240, n=10240, k=192, dtype="f64", seed=2, variant="left"),
+    # 2x2 reflectors (tau, nu) in place of (c, s)
+    "refl-f64-10240-k192": dict(m=10240, n=10240, k=192, dtype="f64", seed=2, variant="refl"),
 }
 BATCHED = {"batched-f64-512": dict(count=512, seed=4, dtype="f64")}
 SERVED = {"served-f64": dict(seed=5, n_lo=128, n_hi=4096, sweeps=20, ks=(16, 32, 64, 128),
@@ -101,6 +105,38 @@ def cpu_baseline(pb, dtype, target_s=15.0):
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} of {m} rows x all {n} columns x all {k} sequences "
                       f"({dt:.1f} s, FP64 oracle, row-partitioned threads)"}
+
+
+def cpu_baseline_variant(pb, variant, target_s=8.0):
+    """The oracle's loop for left application or reflectors (one thread) on a
+    bounded sample: columns for left application (they are independent),
+    rows for reflectors."""
+    import numpy as np
+    import oracle
+    A = np.asarray(pb.A)
+    C, S = oracle.colmajor(np.asarray(pb.C)), oracle.colmajor(np.asarray(pb.S))
+    m, n, k = pb.m, pb.n, pb.k
+    left = variant == "left"
+    total = n if left else m
+
+    def timed(cnt):
+        sub = oracle.colmajor(A[:, :cnt] if left else A[:cnt])
+        t0 = time.perf_counter()
+        if left:
+            oracle.rotseq(sub, C, S, left=True)
+        else:
+            oracle.reflseq(sub, C, S)
+        return time.perf_counter() - t0
+
+    cnt = 2
+    dt = timed(cnt)
+    cnt = int(min(total, max(cnt, cnt * target_s / max(dt, 1e-3))))
+    dt = timed(cnt)
+    r = (m - 1) if left else (n - 1)
+    gf = 6.0 * cnt * r * k / dt / 1e9
+    what = f"{cnt} of {n} columns x all {m} rows" if left else f"{cnt} of {m} rows x all {n} columns"
+    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} x all {k} sequences ({dt:.1f} s, FP64 oracle, one thread)"}
 
 
 def bench_batched(args):
@@ -356,28 +392,38 @@ def main():
     import numpy as np
     import torch
     import paper_2412_01852_amd as rs
-    from paper_2412_01852_amd.inputs import make_problem
+    from paper_2412_01852_amd.inputs import make_left_problem, make_problem, make_refl_problem
 
     wl = WORKLOADS[args.workload]
     m, n, k, dtype = wl["m"], wl["n"], wl["k"], wl["dtype"]
+    variant = wl.get("variant", "right")
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    pb = make_problem(m, n, k, seed=wl["seed"])
+    make = {"right": make_problem, "left": make_left_problem, "refl": make_refl_problem}[variant]
+    pb = make(m, n, k, seed=wl["seed"])
     A = rs.device_colmajor(pb.A, "cuda:0", tdt)
     C = rs.device_colmajor(pb.C, "cuda:0", tdt)
     S = rs.device_colmajor(pb.S, "cuda:0", tdt)
-    flops = 6.0 * m * (n - 1) * k
+    # counted work: 6 flops per (rotation or reflector, entry it updates)
+    flops = 6.0 * (n * (m - 1) if variant == "left" else m * (n - 1)) * k
     esize = 8 if dtype == "f64" else 4
-    alg_bytes = esize * (2.0 * m * n + 2.0 * (n - 1) * k)
+    nrot = (m - 1) if variant == "left" else (n - 1)
+    alg_bytes = esize * (2.0 * m * n + 2.0 * nrot * k)
+    if variant == "right":
+        step = lambda: rs.rotseq(A, C, S)  # noqa: E731
+    elif variant == "left":
+        step = lambda: rs.rotseq(A, C, S, opts={"left": 1})  # noqa: E731
+    else:
+        step = lambda: rs.reflseq(A, C, S)  # noqa: E731
 
     for _ in range(args.warmup):
-        rs.rotseq(A, C, S)
+        step()
     torch.cuda.synchronize()
     rs.profile_read(reset=True)
     rs.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rs.rotseq(A, C, S)
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rs.profile_enable(False)
@@ -402,9 +448,13 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
-        "data": "synthetic (A iid N(0,1), angles iid U[0,2pi), seeded PCG64)",
+        "data": "synthetic (A iid N(0,1), angles iid U[0,2pi), seeded PCG64)" if variant != "refl"
+                else "synthetic (A iid N(0,1), reflectors nu = tan(phi), phi iid U(-pi/2,pi/2), "
+                     "tau = 2/(1+nu^2), 5% tau = 0; seeded PCG64)",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "lda": m,
-                   "arith": "lift", "parallelism": "single GPU"},
+                   "arith": "lift", "parallelism": "single GPU",
+                   "sequences_mix": "rows" if variant == "left" else "columns",
+                   "elements": "reflectors" if variant == "refl" else "rotations"},
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),
@@ -420,8 +470,12 @@ def main():
             "hbm_bound_ms": round(alg_bytes / (HBM_GBS * 1e9) * 1e3, 4),
         },
     }
+    if variant == "left":
+        # prep_ms includes packing A^T into the workspace and unpacking it
+        out["roofline"]["packing_bytes"] = 4.0 * esize * m * n
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pb, dtype, args.cpu_seconds)
+        out["cpu_baseline"] = (cpu_baseline(pb, dtype, args.cpu_seconds) if variant == "right"
+                               else cpu_baseline_variant(pb, variant))
     print(json.dumps(out), flush=True)
     return 0
 

@@ -9,8 +9,11 @@
 // consecutive ones are packed W to a workgroup (one wave each), so a
 // workgroup holds a chain of bands of one tile, or the tail of one tile's
 // chain and the head of the next.  Inside a workgroup, column hand-off
-// between neighbours in a chain goes through an LDS ring of RB column slots
-// with produced/consumed counters.  Where a chain crosses a workgroup
+// between neighbours in a chain goes through an LDS ring of RB column slots,
+// and the waves advance in lockstep groups of steps separated by workgroup
+// barriers, each wave a fixed number of groups behind the one it reads
+// from, so a slot is never read before it is written nor overwritten before
+// it is read.  Where a chain crosses a workgroup
 // boundary, the producer writes the columns to A in place with device-scope
 // (write-through) stores and publishes how many leading columns are complete
 // in a device-scope counter; the consumer polls that counter and reads A
@@ -21,9 +24,10 @@
 // With W chosen so that the number of workgroups matches the number of CUs,
 // every CU gets the same amount of work regardless of how m relates to 64.
 //
-// Every wait is bounded: after `spin_limit` polls a wave records
-// ROTSEQ_E_TIMEOUT in the status word and carries on with whatever data it
-// has, so the grid always drains.  All accesses stay in bounds whatever the
+// Every wait on another workgroup is bounded: after `spin_limit` polls a wave
+// records ROTSEQ_E_TIMEOUT in the status word and carries on with whatever
+// data it has, so the grid always drains; every wave of a workgroup passes
+// the same number of barriers.  All accesses stay in bounds whatever the
 // data (buffer descriptors for A, ring indices modulo RB for LDS).
 #include <type_traits>
 
@@ -49,7 +53,14 @@ struct ChainGeom {
     static constexpr int R_glob = 16;                 // ring of A-fed waves
     static constexpr int D_lds = R_lds - K - 1;
     static constexpr int D_glob = R_glob - K - 1;
-    static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0, "geometry");
+    static constexpr int G = 4;                       // steps per lockstep group
+    // Groups between the starts of neighbouring waves of a chain segment:
+    // the smallest lag for which every LDS column slot is written, read and
+    // overwritten in three different groups, in that order.
+    static constexpr int LG = K == 8 ? 5 : 3;
+    static_assert(K == 4 || K == 6 || K == 8, "band widths of the chain kernel");
+    static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0 && U % G == 0,
+                  "geometry");
 };
 
 struct ChainArgs {
@@ -72,10 +83,6 @@ struct ChainArgs {
     int *status;     // error word
 };
 
-// LDS counters: produced[16][64] then consumed[16][64] (one row per wave,
-// one slot per lane; every lane advances its own slot in the same
-// instruction, so any slot, read as slot 0, is the counter).
-constexpr int kCounterWords = 2 * 16 * 64;
 // A producer publishes column c only once its store has completed; it waits
 // for all but the newest kPublishLag stores, so it rarely waits at all.
 constexpr int kPublishLag = 16;
@@ -86,56 +93,38 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 __device__ __forceinline__ void opaque_i(int &x) { asm volatile("" : "+s"(x)); }
 
 // Which wait gave up, recorded in bits 8.. of the status word beside
-// ROTSEQ_E_TIMEOUT: LDS input, LDS output, device-scope flag.
-constexpr int kWaitLdsIn = 1 << 8, kWaitLdsOut = 1 << 9, kWaitFlag = 1 << 10;
+// ROTSEQ_E_TIMEOUT: the device-scope flag between workgroups.
+constexpr int kWaitFlag = 1 << 10;
 
 __device__ __forceinline__ void record_timeout(int *status, int kind)
 {
     __hip_atomic_fetch_or(status, ROTSEQ_E_TIMEOUT | kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until the LDS counter exceeds `need`; returns its value.  After a
-// timeout `limit` drops to 0, so the wave never waits again and the grid
-// drains within one time-out per wave; the kind of wait that gave up is
-// collected in `timed_out` and written to the status word once, when the
-// wave ends (a memory write inside the step loop would make the compiler
-// drain every outstanding vector memory operation at each wait site).
-typedef __attribute__((address_space(3))) volatile int lds_counter;
-
-__device__ __forceinline__ int wait_lds(lds_counter *p, int need, int &limit, int &timed_out, int kind)
+// End of a lockstep group: this wave's LDS accesses have completed (LGKM
+// count 0; vector memory is not waited for), then all waves of the
+// workgroup meet.  The compiler fences keep LDS accesses on their side.
+__device__ __forceinline__ void group_barrier()
 {
-    int v = uniform(*p);
-    for (int polls = 0; v <= need; ++polls) {
-        if (polls >= limit) {
-            timed_out |= kind;
-            limit = 0;
-            return 0x7fffffff;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        v = uniform(*p);
-    }
-    return v;
+    compiler_fence();
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0) only
+    __builtin_amdgcn_s_barrier();
+    compiler_fence();
 }
 
-// Adds 1 to a counter row: each lane to its own slot (`p` = row + lane), one
-// conflict-free ds_add_u32 of the whole wave.  No VALU instruction and no
-// change of the exec mask (a single-lane form costs a SALU exec write and a
-// pipeline bubble before the next VALU instruction, twice per step).
-__device__ __forceinline__ void lds_inc(lds_counter *p)
+// `groups` lockstep groups without work.
+__device__ __forceinline__ void idle_groups(int groups)
 {
-    __hip_atomic_fetch_add((__attribute__((address_space(3))) int *)p, 1, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int i = 0; i < groups; ++i)
+        group_barrier();
 }
 
-// The same LDS address, pinned in a VGPR once, so that lds_inc in the step
-// loop needs no VALU instruction to form its address operand.
-__device__ __forceinline__ lds_counter *addr_in_vgpr(lds_counter *p)
-{
-    uint32_t v = (uint32_t)(uintptr_t)p;
-    asm volatile("" : "+v"(v));
-    return (lds_counter *)(uintptr_t)v;
-}
-
+// Bounded waits: after a timeout `limit` drops to 0, so the wave never waits
+// again and the grid drains within one time-out per wave; the kind of wait
+// that gave up is collected in `timed_out` and written to the status word
+// once, when the wave ends (a memory write inside the step loop would make
+// the compiler drain every outstanding vector memory operation at each wait
+// site).
 // Waits until the device-scope progress counter exceeds `need` (polls cost
 // a memory round trip, so they get a sixteenth of the LDS budget).
 __device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int &timed_out)
@@ -296,39 +285,35 @@ enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel 
 
 // One band-wave, unrolled over U steps.
 //
-// Flow control is per column, evaluated once per group of G = 4 steps.  A
-// consumer (LDS input) may read column c once produced > c; a producer (LDS
-// output) may overwrite the slot of column c - RB once consumed > c - RB.
-// Both counters advance every step (an LDS atomic add after the slot access)
-// and are re-read asynchronously (an LDS load issued one step before the
-// group), so a wave only stalls when its neighbour really is behind.
+// Flow control inside a workgroup is lockstep: the step loop is cut into
+// groups of G steps, and every wave of the workgroup ends every group at the
+// same barrier (group_barrier), after its LDS writes of the group have
+// completed.  A wave at position `pos` of its chain segment (pos = 0 reads
+// A; pos > 0 reads the LDS channel of the wave before it) starts LG*pos
+// groups after the segment's first wave: one group for the prologue's
+// fetches, then its steps.  With that lag every column slot is written in a
+// strictly earlier group than the one that reads it, and read in a strictly
+// earlier group than the one that overwrites it (ChainGeom::LG; checked by
+// tests/test_lockstep_schedule.py for every band width).  Waves then pad the
+// schedule with idle groups, so every wave of the workgroup (idle ones
+// included) passes the same number of barriers: LG*(W-1) + 1 + steps/G.
 //
 // Channel reads and writes are unconditional: columns outside [0, n)
 // travel as data too (zeros, or past n possibly an older finite column of
 // the same row, which only ever meets identity rotations), and A is
 // protected by empty buffer descriptors.
 template <typename T, int K, int ARITH, int IN, int OUT>
-__device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, int w, char *lds_generic)
+__device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, int w, int pos,
+                                         char *lds_generic)
 {
     using Geo = ChainGeom<K>;
     constexpr int U = Geo::U;
     constexpr int RB = Geo::RB;
+    constexpr int G = Geo::G;
     constexpr int R = IN == kInLds ? Geo::R_lds : Geo::R_glob;
     constexpr int D = R - K - 1;
     constexpr int SLOT = kWave;  // elements per ring slot
-    constexpr int G = 4;         // steps per flow-control group
-    // A blocked consumer waits for produced >= lc + G + kInSlack, a blocked
-    // producer for consumed >= sc + G - RB + kOutSlack; the two can never
-    // block each other as long as kInSlack + kOutSlack <= RB + 1 - 2G.  No
-    // extra headroom is asked for: with counters current to the step, a
-    // wave that waits only for what its next group needs resumes soonest
-    // (measured faster than waiting for half the ring).
-    constexpr int kSlack = RB + 1 - 2 * G;
-    constexpr int kInSlack = 0;
-    constexpr int kOutSlack = 0;
     static_assert(U % G == 0, "groups must tile the unroll");
-    static_assert(kInSlack >= 0 && kOutSlack >= 0 && kInSlack + kOutSlack <= kSlack,
-                  "ring too small for the group size");
     typedef __attribute__((address_space(3))) T lds_T;
     const int n = a.n;
     const int lane = threadIdx.x & (kWave - 1);
@@ -341,29 +326,20 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     int limit = a.spin_limit;
     int timed_out = 0;
 
-    __attribute__((address_space(3))) char *lds = (__attribute__((address_space(3))) char *)lds_generic;
-    lds_counter *cnt = (lds_counter *)lds;
-    lds_T *rings = (lds_T *)(lds + kCounterWords * sizeof(int));
-    lds_counter *prod_in = cnt + (w - 1) * kWave, *cons_in = cnt + (16 + w - 1) * kWave;
-    lds_counter *prod_out = cnt + w * kWave, *cons_out = cnt + (16 + w) * kWave;
-    lds_counter *cons_in_v = addr_in_vgpr(cons_in + lane), *prod_out_v = addr_in_vgpr(prod_out + lane);
+    lds_T *rings = (lds_T *)(__attribute__((address_space(3))) char *)lds_generic;
     lds_T *ring_in = rings + (w - 1) * RB * SLOT + lane;
     lds_T *ring_out = rings + w * RB * SLOT + lane;
     int *flag_in = a.flags + (int64_t)tile * a.nbands + (b - 1);
     int *flag_out = a.flags + (int64_t)tile * a.nbands + b;
     const int pubmask = a.publish - 1;
 
-    // Input columns < in_known exist; the LDS consumer has read columns
-    // < out_known.  in_poll / out_poll: counter values read one step (LDS)
-    // or one group (flag) before the group that uses them.
-    //
-    // LDS counters count steps: a producer adds 1 after writing each output
-    // slot (its first kLead steps output columns < 0), a consumer adds 1
-    // after reading each input slot, so both are current to the step.
-    constexpr int kLead = K - 1;
-    int in_known = IN == kInFresh ? 0x7fffffff : 0;
-    int out_known = 0;
-    int in_poll = 0, out_poll = 0;
+    // Wait for the wave's place in the segment's schedule.
+    idle_groups(Geo::LG * pos);
+
+    // Input columns < in_known exist (A-fed waves after a flag wait; LDS-fed
+    // waves rely on the schedule).  in_poll: the flag read one group early.
+    int in_known = IN == kInWait ? 0 : 0x7fffffff;
+    int in_poll = 0;
 
     T ring[R];
 #pragma unroll
@@ -374,14 +350,10 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     int lc = 0;
     uint64_t lp = tileaddr;
     auto ensure_in = [&](int cols) {  // the next `cols` fetches must exist
-        if constexpr (IN != kInFresh) {
+        if constexpr (IN == kInWait) {
             if (lc + cols > in_known && lc < n) {
-                const int want = lc + cols + kInSlack;
-                const int need = (want < n ? want : n) - 1;
-                if constexpr (IN == kInLds)
-                    in_known = wait_lds(prod_in, need + kLead, limit, timed_out, kWaitLdsIn) - kLead;
-                else
-                    in_known = wait_flag(flag_in, need, limit, timed_out);
+                const int want = lc + cols;
+                in_known = wait_flag(flag_in, (want < n ? want : n) - 1, limit, timed_out);
             }
         }
     };
@@ -396,20 +368,15 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         ++lc;
     };
 
+    // Prologue group: the first D+1 columns.
     ensure_in(D + 1);
 #pragma unroll
     for (int c = 0; c <= D; ++c)
         fetch(ring[c], c % RB);
     opaque_i(lc);
-    if constexpr (IN == kInLds) {
-        compiler_fence();
-        *cons_in_v = lc;
-        in_poll = *prod_in;
-    } else if constexpr (IN == kInWait) {
+    if constexpr (IN == kInWait)
         in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if constexpr (OUT == kOutLds)
-        out_poll = *cons_out;
+    group_barrier();
 
     // Output stream: next output column sc (at address sp in A).
     int sc = -(K - 1);
@@ -471,8 +438,6 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         T val = ring[(uu - K + 1 + U) % R];
         if constexpr (OUT == kOutLds) {
             ring_out[((uu - K + 1 + U) % RB) * SLOT] = val;
-            compiler_fence();
-            lds_inc(prod_out_v);
         } else {
             const int c = sc + (uu % G);
             const bool valid = (unsigned)c < (unsigned)n;
@@ -502,30 +467,15 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     for (int t0 = 0; t0 < a.steps; t0 += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (u % G == 0) {
-                // Group prologue: fold in the counters polled earlier, make
-                // sure this group's G fetches and G slot writes are allowed,
-                // and re-read the flag for the next group.
-                if constexpr (IN == kInLds || IN == kInWait) {
-                    const int v = uniform(in_poll) - (IN == kInLds ? kLead : 0);
+            if constexpr (IN == kInWait) {
+                if (u % G == 0) {
+                    // Fold in the flag read a group ago, make sure this group's
+                    // G fetches exist, and re-read the flag for the next group.
+                    const int v = uniform(in_poll);
                     in_known = v > in_known ? v : in_known;
-                }
-                ensure_in(G);
-                if constexpr (OUT == kOutLds) {
-                    const int v = uniform(out_poll);
-                    out_known = v > out_known ? v : out_known;
-                    if (sc + G > out_known + RB)  // slot of column sc+G-1-RB must be read
-                        out_known = wait_lds(cons_out, sc + G - 1 - RB + kOutSlack, limit, timed_out, kWaitLdsOut);
-                }
-                if constexpr (IN == kInWait)
+                    ensure_in(G);
                     in_poll = __hip_atomic_load(flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (u % G == G - 1) {
-                // Poll the LDS counters one step before the next group needs them.
-                if constexpr (IN == kInLds)
-                    in_poll = *prod_in;
-                if constexpr (OUT == kOutLds)
-                    out_poll = *cons_out;
+                }
             }
             // Coefficients of this step (lanes OFF..OFF+K-1 of each row of
             // `cur`); a new record group replaces the one just taken, kAhead
@@ -536,10 +486,6 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
             }
             // Column t+1+D replaces column t-K, finished last step.
             fetch(ring[(u + D + 1) % R], (u + D + 1) % RB);
-            if constexpr (IN == kInLds) {
-                compiler_fence();
-                lds_inc(cons_in_v);
-            }
             select_const<SPL>(u % SPL, [&](auto jc) {
                 constexpr int OFF = decltype(jc)::value * K;
                 if constexpr (sizeof(T) == 8 && ARITH == kLift) {
@@ -569,6 +515,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                 sc += G;
                 opaque_i(lc);
                 opaque_i(sc);
+                group_barrier();
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -594,20 +541,22 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         wait_vmem_at_most<0>();
         __hip_atomic_store(flag_out, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // Pad the schedule to the workgroup's common barrier count.
+    idle_groups(Geo::LG * (a.waves - 1 - pos));
     if (timed_out)
         record_timeout(a.status, timed_out);
 }
 
 template <typename T, int K, int ARITH, int IN>
-__device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b, int w, char *lds,
-                                             int out)
+__device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b, int w, int pos,
+                                             char *lds, int out)
 {
     if (out == kOutLds)
-        bandwave<T, K, ARITH, IN, kOutLds>(a, tile, b, w, lds);
+        bandwave<T, K, ARITH, IN, kOutLds>(a, tile, b, w, pos, lds);
     else if (out == kOutPublish)
-        bandwave<T, K, ARITH, IN, kOutPublish>(a, tile, b, w, lds);
+        bandwave<T, K, ARITH, IN, kOutPublish>(a, tile, b, w, pos, lds);
     else
-        bandwave<T, K, ARITH, IN, kOutFinal>(a, tile, b, w, lds);
+        bandwave<T, K, ARITH, IN, kOutFinal>(a, tile, b, w, pos, lds);
 }
 
 // Workgroup g of a problem's chain grid: its waves take the (tile, band)
@@ -618,25 +567,30 @@ __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char 
     const int w = uniform((int)(threadIdx.x >> 6));
     const int64_t idx = (int64_t)g * a.waves + w;
     const int64_t total = (int64_t)a.tiles * a.nbands;
-    if (idx >= total)
+    if (idx >= total) {
+        // No unit: keep the workgroup's barrier count.
+        idle_groups(ChainGeom<K>::LG * (a.waves - 1) + 1 + a.steps / ChainGeom<K>::G);
         return;
+    }
     const int tile = (int)(idx / a.nbands);
     const int b = (int)(idx - (int64_t)tile * a.nbands);
     // The previous wave of this workgroup holds band b-1 of the same tile
-    // exactly when b > 0; likewise the next wave holds band b+1.
+    // exactly when b > 0; likewise the next wave holds band b+1.  The
+    // segment of this tile in the workgroup starts min(w, b) waves back.
+    const int pos = w < b ? w : b;
     const int in = (w > 0 && b > 0) ? kInLds : (b == 0 ? kInFresh : kInWait);
     const int out = (w + 1 < a.waves && b + 1 < a.nbands) ? kOutLds
                     : (b + 1 < a.nbands ? kOutPublish : kOutFinal);
     if (in == kInLds)
-        bandwave_out<T, K, ARITH, kInLds>(a, tile, b, w, lds, out);
+        bandwave_out<T, K, ARITH, kInLds>(a, tile, b, w, pos, lds, out);
     else if (in == kInFresh)
-        bandwave_out<T, K, ARITH, kInFresh>(a, tile, b, w, lds, out);
+        bandwave_out<T, K, ARITH, kInFresh>(a, tile, b, w, pos, lds, out);
     else
-        bandwave_out<T, K, ARITH, kInWait>(a, tile, b, w, lds, out);
+        bandwave_out<T, K, ARITH, kInWait>(a, tile, b, w, pos, lds, out);
 }
 
-// Zeroes the workgroup's LDS: counters start at 0, and rings start as zeros
-// so that a column slot read before its first write holds a finite value.
+// Zeroes the workgroup's LDS rings, so that a column slot read before its
+// first write (only columns past the band's last output) holds a finite value.
 __device__ __forceinline__ void zero_lds(char *lds, uint32_t words)
 {
     for (uint32_t i = threadIdx.x; i < words; i += blockDim.x)
@@ -815,7 +769,9 @@ int chain_unroll(int band)
 size_t chain_lds_bytes(int band, int waves, int esize)
 {
     (void)band;
-    return kCounterWords * sizeof(int) + (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
+    // at least one word, so that the zeroing loop has a valid extent
+    const size_t rings = (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
+    return rings > 0 ? rings : 4;
 }
 
 hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,

@@ -404,7 +404,9 @@ __global__ void prep_zero(int *__restrict__ p, int64_t count)
 // contiguous columns the sweep streams.  One 256-thread workgroup moves a
 // 64 x 64 tile through LDS: it reads 64-element column segments of the
 // source (512 B for FP64, one per wave and instruction) and writes 64-element
-// column segments of the destination, so both sides are coalesced.  The tile
+// column segments of the destination, so both sides are coalesced.  Each
+// thread keeps all 16 of its loads in flight (about 128 KB per CU at four
+// workgroups, enough to cover HBM latency at full bandwidth).  The tile
 // has one padding column, which spreads a transposed read of LDS over all
 // banks.
 
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(256) void transpose_tiles(const T *__restrict__ src
     for (int64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
         const int64_t r0 = (tid % tiles_r) * kTile, c0 = (tid / tiles_r) * kTile;
         const int64_t r = r0 + lane;
-#pragma unroll 4
+#pragma unroll
         for (int cc = wave; cc < kTile; cc += 4) {
             const int64_t c = c0 + cc;
             if (r < rows && c < cols)
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(256) void transpose_tiles(const T *__restrict__ src
         __syncthreads();
         // dst(c, r) = src(r, c): destination column r holds source row r.
         const int64_t c = c0 + lane;
-#pragma unroll 4
+#pragma unroll
         for (int rr = wave; rr < kTile; rr += 4) {
             const int64_t rw = r0 + rr;
             if (rw < rows && c < cols)
