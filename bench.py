@@ -96,11 +96,15 @@ def cpu_baseline(pb, dtype, target_s=15.0):
         oracle.rotseq(sub, Cw, Sw, threads=threads)
         return time.perf_counter() - t0
 
+    # Grow the sample until it takes at least half the target time (small
+    # samples are dominated by thread start-up, so one extrapolation from
+    # them undershoots), then time it.
     rows = min(m, 4 * threads)
     dt = timed(rows)
-    rows = int(min(m, max(rows, rows * target_s / max(dt, 1e-3))))
-    rows = max(threads, (rows // threads) * threads) if rows >= threads else rows
-    dt = timed(rows)
+    while dt < 0.5 * target_s and rows < m:
+        rows = int(min(m, max(2 * rows, rows * target_s / max(dt, 1e-3))))
+        rows = max(threads, (rows // threads) * threads) if rows >= threads else rows
+        dt = timed(rows)
     gf = 6.0 * rows * (n - 1) * k / dt / 1e9
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} of {m} rows x all {n} columns x all {k} sequences "
@@ -128,10 +132,11 @@ def cpu_baseline_variant(pb, variant, target_s=8.0):
             oracle.reflseq(sub, C, S)
         return time.perf_counter() - t0
 
-    cnt = 2
+    cnt = 8
     dt = timed(cnt)
-    cnt = int(min(total, max(cnt, cnt * target_s / max(dt, 1e-3))))
-    dt = timed(cnt)
+    while dt < 0.5 * target_s and cnt < total:
+        cnt = int(min(total, max(2 * cnt, cnt * target_s / max(dt, 1e-3))))
+        dt = timed(cnt)
     r = (m - 1) if left else (n - 1)
     gf = 6.0 * cnt * r * k / dt / 1e9
     what = f"{cnt} of {n} columns x all {m} rows" if left else f"{cnt} of {m} rows x all {n} columns"
