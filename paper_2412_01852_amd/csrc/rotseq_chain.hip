@@ -58,6 +58,13 @@ struct ChainGeom {
     // the smallest lag for which every LDS column slot is written, read and
     // overwritten in three different groups, in that order.
     static constexpr int LG = K == 8 ? 5 : 3;
+    // Groups from the start of a workgroup's wave that publishes through A to
+    // the start of the wave in the next workgroup that reads it, so that the
+    // reader rarely waits (a wait inside a lockstep group holds up its whole
+    // workgroup): publication is per 16-column block, 16 columns behind the
+    // newest store, and a group needs G + D_glob columns ahead, so the reader
+    // trails by about 14 groups; 2 more cover the flag's latency.
+    static constexpr int DG = 16;
     static_assert(K == 4 || K == 6 || K == 8, "band widths of the chain kernel");
     static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0 && U % G == 0,
                   "geometry");
@@ -294,16 +301,18 @@ enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel 
 // fetches, then its steps.  With that lag every column slot is written in a
 // strictly earlier group than the one that reads it, and read in a strictly
 // earlier group than the one that overwrites it (ChainGeom::LG; checked by
-// tests/test_lockstep_schedule.py for every band width).  Waves then pad the
-// schedule with idle groups, so every wave of the workgroup (idle ones
-// included) passes the same number of barriers: LG*(W-1) + 1 + steps/G.
+// tests/test_lockstep_schedule.py for every band width).  A segment fed
+// through A by the previous workgroup starts later still (segment_offset).
+// `pre` idle groups come before the wave's prologue and `post` after its
+// steps, so that every wave of the workgroup (idle ones included) passes the
+// same number of barriers: the workgroup's largest `pre` + 1 + steps/G.
 //
 // Channel reads and writes are unconditional: columns outside [0, n)
 // travel as data too (zeros, or past n possibly an older finite column of
 // the same row, which only ever meets identity rotations), and A is
 // protected by empty buffer descriptors.
 template <typename T, int K, int ARITH, int IN, int OUT>
-__device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, int w, int pos,
+__device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, int w, int pre, int post,
                                          char *lds_generic)
 {
     using Geo = ChainGeom<K>;
@@ -333,8 +342,8 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     int *flag_out = a.flags + (int64_t)tile * a.nbands + b;
     const int pubmask = a.publish - 1;
 
-    // Wait for the wave's place in the segment's schedule.
-    idle_groups(Geo::LG * pos);
+    // Wait for the wave's place in the workgroup's schedule.
+    idle_groups(pre);
 
     // Input columns < in_known exist (A-fed waves after a flag wait; LDS-fed
     // waves rely on the schedule).  in_poll: the flag read one group early.
@@ -542,21 +551,39 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         __hip_atomic_store(flag_out, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // Pad the schedule to the workgroup's common barrier count.
-    idle_groups(Geo::LG * (a.waves - 1 - pos));
+    idle_groups(post);
     if (timed_out)
         record_timeout(a.status, timed_out);
 }
 
 template <typename T, int K, int ARITH, int IN>
-__device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b, int w, int pos,
-                                             char *lds, int out)
+__device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b, int w, int pre,
+                                             int post, char *lds, int out)
 {
     if (out == kOutLds)
-        bandwave<T, K, ARITH, IN, kOutLds>(a, tile, b, w, pos, lds);
+        bandwave<T, K, ARITH, IN, kOutLds>(a, tile, b, w, pre, post, lds);
     else if (out == kOutPublish)
-        bandwave<T, K, ARITH, IN, kOutPublish>(a, tile, b, w, pos, lds);
+        bandwave<T, K, ARITH, IN, kOutPublish>(a, tile, b, w, pre, post, lds);
     else
-        bandwave<T, K, ARITH, IN, kOutFinal>(a, tile, b, w, pos, lds);
+        bandwave<T, K, ARITH, IN, kOutFinal>(a, tile, b, w, pre, post, lds);
+}
+
+// Groups by which a chain segment that starts at band b0 is held back in its
+// workgroup's lockstep schedule.  A segment with b0 > 0 starts at wave 0 and
+// reads band b0-1 through A from the last wave of the previous workgroup,
+// which is at position r-1 = min(W, b0)-1 of a segment starting at band
+// b0-r; that wave starts LG*(r-1) groups after its own segment, and its
+// output trails it by DG groups.  Hence, with b0 = q*W + r (1 <= r <= W),
+// the offset is q*(LG*(W-1) + DG) + LG*(r-1) + DG.
+template <int K>
+__device__ __forceinline__ int segment_offset(int b0, int W)
+{
+    if (b0 <= 0)
+        return 0;
+    constexpr int LG = ChainGeom<K>::LG, DG = ChainGeom<K>::DG;
+    const int r = (b0 - 1) % W + 1;
+    const int q = (b0 - r) / W;
+    return q * (LG * (W - 1) + DG) + LG * (r - 1) + DG;
 }
 
 // Workgroup g of a problem's chain grid: its waves take the (tile, band)
@@ -564,29 +591,44 @@ __device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b
 template <typename T, int K, int ARITH>
 __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char *lds)
 {
+    constexpr int LG = ChainGeom<K>::LG;
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int64_t idx = (int64_t)g * a.waves + w;
     const int64_t total = (int64_t)a.tiles * a.nbands;
+    // Idle groups before each wave's prologue: its segment's offset plus LG
+    // per position.  The previous wave of this workgroup holds band b-1 of
+    // the same tile exactly when b > 0, so a wave's segment starts min(w, b)
+    // waves back.  Every wave computes the workgroup's largest one the same
+    // way, which fixes the common barrier count.
+    int pre = 0, max_pre = 0;
+    for (int v = 0; v < a.waves; ++v) {
+        const int64_t iv = (int64_t)g * a.waves + v;
+        if (iv >= total)
+            break;
+        const int bv = (int)(iv % a.nbands);
+        const int pv = v < bv ? v : bv;
+        const int pre_v = segment_offset<K>(bv - pv, a.waves) + LG * pv;
+        max_pre = pre_v > max_pre ? pre_v : max_pre;
+        if (v == w)
+            pre = pre_v;
+    }
+    const int64_t idx = (int64_t)g * a.waves + w;
     if (idx >= total) {
         // No unit: keep the workgroup's barrier count.
-        idle_groups(ChainGeom<K>::LG * (a.waves - 1) + 1 + a.steps / ChainGeom<K>::G);
+        idle_groups(max_pre + 1 + a.steps / ChainGeom<K>::G);
         return;
     }
     const int tile = (int)(idx / a.nbands);
     const int b = (int)(idx - (int64_t)tile * a.nbands);
-    // The previous wave of this workgroup holds band b-1 of the same tile
-    // exactly when b > 0; likewise the next wave holds band b+1.  The
-    // segment of this tile in the workgroup starts min(w, b) waves back.
-    const int pos = w < b ? w : b;
     const int in = (w > 0 && b > 0) ? kInLds : (b == 0 ? kInFresh : kInWait);
     const int out = (w + 1 < a.waves && b + 1 < a.nbands) ? kOutLds
                     : (b + 1 < a.nbands ? kOutPublish : kOutFinal);
+    const int post = max_pre - pre;
     if (in == kInLds)
-        bandwave_out<T, K, ARITH, kInLds>(a, tile, b, w, pos, lds, out);
+        bandwave_out<T, K, ARITH, kInLds>(a, tile, b, w, pre, post, lds, out);
     else if (in == kInFresh)
-        bandwave_out<T, K, ARITH, kInFresh>(a, tile, b, w, pos, lds, out);
+        bandwave_out<T, K, ARITH, kInFresh>(a, tile, b, w, pre, post, lds, out);
     else
-        bandwave_out<T, K, ARITH, kInWait>(a, tile, b, w, pos, lds, out);
+        bandwave_out<T, K, ARITH, kInWait>(a, tile, b, w, pre, post, lds, out);
 }
 
 // Zeroes the workgroup's LDS rings, so that a column slot read before its

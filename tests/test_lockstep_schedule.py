@@ -13,9 +13,9 @@ and nothing inside it, so hand-off through a slot is safe exactly when, for
 every column c, the producer's write group < the consumer's read group <
 the group of the producer's next write to the same slot.  The test checks
 that with the kernel's constants for every band width, that one group less
-of lag breaks it (so the lag is the smallest), and that every wave passes
-the same number of barriers whatever its position, which is what keeps the
-barrier from deadlocking.
+of lag breaks it (so the lag is the smallest), and that every wave of every
+workgroup passes the same number of barriers whatever its position and
+segment offset, which keeps the barriers matched.
 """
 import os
 import re
@@ -88,13 +88,85 @@ def test_too_much_lag_overwrites(K):
                for kind, _ in violations(K, kernel_lag(K) + RB // G, 10256))
 
 
+def kernel_dg():
+    src = open(CHAIN).read()
+    return int(re.search(r"static constexpr int DG = (\d+);", src).group(1))
+
+
+def segment_offset(b0, W, lg, dg):
+    """The kernel's closed form (segment_offset in the chain kernel)."""
+    if b0 <= 0:
+        return 0
+    r = (b0 - 1) % W + 1
+    q = (b0 - r) // W
+    return q * (lg * (W - 1) + dg) + lg * (r - 1) + dg
+
+
+def segment_offset_recursive(b0, W, lg, dg):
+    """The definition: a segment starting at band b0 > 0 follows the last
+    wave of the previous workgroup, at position min(W, b0) - 1 of a segment
+    starting at band b0 - min(W, b0), by DG groups."""
+    if b0 == 0:
+        return 0
+    r = min(W, b0)
+    return segment_offset_recursive(b0 - r, W, lg, dg) + lg * (r - 1) + dg
+
+
+@pytest.mark.parametrize("W", [1, 2, 3, 8, 15, 16])
+def test_segment_offset_closed_form(W):
+    lg, dg = kernel_lag(8), kernel_dg()
+    for b0 in range(0, 200):
+        assert segment_offset(b0, W, lg, dg) == segment_offset_recursive(b0, W, lg, dg)
+
+
+def workgroup_barriers(g, W, tiles, nbands, steps, lg, dg):
+    """Barriers each wave of workgroup g passes, following chain_workgroup
+    and bandwave: pre idle groups, the prologue group, steps/G groups, post
+    idle groups; idle waves pass max_pre + 1 + steps/G."""
+    total = tiles * nbands
+    pres = []
+    for v in range(W):
+        iv = g * W + v
+        if iv >= total:
+            break
+        bv = iv % nbands
+        pv = min(v, bv)
+        pres.append(segment_offset(bv - pv, W, lg, dg) + lg * pv)
+    max_pre = max(pres) if pres else 0
+    counts = []
+    for w in range(W):
+        if g * W + w >= total:
+            counts.append(max_pre + 1 + steps // G)
+        else:
+            pre = pres[w]
+            counts.append(pre + 1 + steps // G + (max_pre - pre))
+    return counts
+
+
 @pytest.mark.parametrize("K", [4, 6, 8])
-@pytest.mark.parametrize("waves", [1, 2, 8, 16])
-def test_every_wave_passes_the_same_barriers(K, waves):
-    """Barrier count per wave as the kernel runs it: idle waves and every
-    position in a segment end up at LG*(W-1) + 1 + steps/G."""
-    lg, steps = kernel_lag(K), 10256 // U * U
-    idle = lg * (waves - 1) + 1 + steps // G
-    for pos in range(waves):
-        active = lg * pos + 1 + steps // G + lg * (waves - 1 - pos)
-        assert active == idle
+@pytest.mark.parametrize("W,tiles,nbands", [(1, 3, 5), (2, 5, 3), (8, 7, 24), (16, 160, 24),
+                                           (16, 3, 5), (15, 11, 40), (16, 2, 100)])
+def test_every_wave_passes_the_same_barriers(K, W, tiles, nbands):
+    """Every wave of every workgroup (idle waves of the last one included)
+    passes the same number of barriers."""
+    lg, dg, steps = kernel_lag(K), kernel_dg(), 10256 // U * U
+    nwg = -(-tiles * nbands // W)
+    for g in range(nwg):
+        counts = workgroup_barriers(g, W, tiles, nbands, steps, lg, dg)
+        assert len(set(counts)) == 1, (g, counts)
+
+
+def test_offsets_keep_neighbours_in_a_segment_lg_apart():
+    """Within a segment the lag between neighbours stays LG (the LDS
+    hand-off condition); segments only move as a whole."""
+    lg, dg, W, nbands = kernel_lag(8), kernel_dg(), 16, 24
+    for g in range(30):
+        prev = None
+        for v in range(W):
+            iv = g * W + v
+            bv, tile = iv % nbands, iv // nbands
+            pv = min(v, bv)
+            pre = segment_offset(bv - pv, W, lg, dg) + lg * pv
+            if prev is not None and prev[0] == tile and pv > 0:
+                assert pre - prev[1] == lg
+            prev = (tile, pre)
