@@ -480,14 +480,25 @@ __device__ __forceinline__ int find_item(const BatchItem *__restrict__ items, in
     return lo;
 }
 
+// One search per workgroup: thread 0 finds the item of the workgroup's first
+// index, and each thread steps forward from there past the (rarely more
+// than one) item boundaries inside the workgroup's range.
 template <typename T, int STAGE>
 __global__ void prep_batch(const BatchItem *__restrict__ items, int count, int64_t total, int K,
                            int arith)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int first_item;
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x == 0)
+        first_item = find_item<STAGE>(items, count, base < total ? base : total - 1);
+    __syncthreads();
+    const int64_t idx = base + threadIdx.x;
     if (idx >= total)
         return;
-    const BatchItem &it = items[find_item<STAGE>(items, count, idx)];
+    int item = first_item;
+    while (item + 1 < count && stage_off<STAGE>(items[item + 1]) <= idx)
+        ++item;
+    const BatchItem &it = items[item];
     const int64_t i = idx - stage_off<STAGE>(it);
     const int64_t n1 = it.n - 1;
     if constexpr (STAGE == kStageNegmask)
