@@ -423,17 +423,23 @@ __global__ __launch_bounds__(256) void transpose_tiles(const T *__restrict__ src
     for (int64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
         const int64_t r0 = (tid % tiles_r) * kTile, c0 = (tid / tiles_r) * kTile;
         const int64_t r = r0 + lane;
+        // Constant trip counts, so that the loops unroll and all 16 loads
+        // are issued before the first LDS write waits for one.
+        T v[kTile / 4];
 #pragma unroll
-        for (int cc = wave; cc < kTile; cc += 4) {
-            const int64_t c = c0 + cc;
-            if (r < rows && c < cols)
-                tile[cc][lane] = src[r + c * lds_src];
+        for (int i = 0; i < kTile / 4; ++i) {
+            const int64_t c = c0 + wave + 4 * i;
+            v[i] = r < rows && c < cols ? src[r + c * lds_src] : T(0);
         }
+#pragma unroll
+        for (int i = 0; i < kTile / 4; ++i)
+            tile[wave + 4 * i][lane] = v[i];
         __syncthreads();
         // dst(c, r) = src(r, c): destination column r holds source row r.
         const int64_t c = c0 + lane;
 #pragma unroll
-        for (int rr = wave; rr < kTile; rr += 4) {
+        for (int i = 0; i < kTile / 4; ++i) {
+            const int rr = wave + 4 * i;
             const int64_t rw = r0 + rr;
             if (rw < rows && c < cols)
                 dst[c + rw * ldd] = tile[lane][rr];
