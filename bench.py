@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -50,13 +51,21 @@ DEFAULT = "plain-f64-10240-k192"
 SWEEP_SOURCES = ("rotseq_chain.hip", "rotseq_device.h", "rotseq_internal.h")
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed, so that
+    editing a comment does not invalidate counter figures."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """Hash of the sources the sweep kernel is compiled from."""
+    """Hash of the code (comments excluded) the sweep kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2412_01852_amd", "csrc")
     for f in SWEEP_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

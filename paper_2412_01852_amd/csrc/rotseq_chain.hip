@@ -40,11 +40,11 @@ using namespace dev;
 namespace {
 
 // Geometry of the chain kernel.  A wave's register ring holds R = K + 1 + D
-// columns, D being how many steps ahead a column is fetched: far ahead from
-// A (HBM latency), one step ahead from an LDS channel.  Each LDS channel has
-// RB = 16 column slots.  The step loop is unrolled U = 16 steps, a multiple
-// of every R and of RB, so every ring, slot and coefficient index in the body
-// is a compile-time constant.
+// columns, D being how many steps ahead a column is fetched: as far as the
+// ring allows, from A (HBM latency) and from an LDS channel alike.  Each LDS
+// channel has RB = 16 column slots.  The step loop is unrolled U = 16 steps,
+// a multiple of every R and of RB, so every ring, slot and coefficient index
+// in the body is a compile-time constant.
 template <int K>
 struct ChainGeom {
     static constexpr int U = 16;

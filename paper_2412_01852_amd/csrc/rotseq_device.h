@@ -77,9 +77,8 @@ __device__ __forceinline__ void wait_vmem_at_most()
 __device__ __forceinline__ void opaque(uint64_t &x) { asm volatile("" : "+s"(x)); }
 
 // Compiler-only ordering point: memory operations are not moved across it.
-// LDS operations of one wave execute in program order in hardware, so this
-// is all a producer/consumer hand-off through LDS needs between its data
-// access and its counter access.
+// The lockstep barrier of the chain kernel puts one on each side of its
+// LDS wait and s_barrier, so no LDS access of a group moves past them.
 __device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
