@@ -322,6 +322,24 @@ int rotseq_batch_create_d(int32_t count, const rotseq_problem_d *probs, const ro
 int rotseq_batch_create_s(int32_t count, const rotseq_problem_s *probs, const rotseq_opts *opts,
                           rotseq_batch **out);
 int rotseq_batch_execute(rotseq_batch *batch, hipStream_t stream);
+/*
+ * rotseq_batch_update_{d,s}: point an existing plan at other buffers.
+ * `probs` lists the same entries as at creation, in the same order and with
+ * the same m, n and k; A, C, S and the leading dimensions may change (and
+ * are checked as at creation, overlap of the A ranges included).  Later
+ * executions, and replays of a graph that captured rotseq_batch_execute,
+ * use the new buffers.
+ *   1 batch   the plan (-1 if NULL)
+ *   2 count   entries (-2 unless it equals the plan's count, or if probs is
+ *             NULL with count > 0; also -2 for a plan of the other type)
+ *   3 probs   host array
+ * An entry whose shape differs returns -(1000*(idx+1) + 1, 2 or 3) for m, n
+ * or k; other invalid entries as rotseq_batch_create_d.  The item table is
+ * rewritten after synchronizing the device, so no execution of the plan may
+ * be in flight.  The plan is unchanged when an error is returned.
+ */
+int rotseq_batch_update_d(rotseq_batch *batch, int32_t count, const rotseq_problem_d *probs);
+int rotseq_batch_update_s(rotseq_batch *batch, int32_t count, const rotseq_problem_s *probs);
 int rotseq_batch_tune(rotseq_batch *batch, hipStream_t stream, int32_t reps);
 int rotseq_batch_info_get(const rotseq_batch *batch, rotseq_batch_info *info);
 int rotseq_batch_destroy(rotseq_batch *batch);

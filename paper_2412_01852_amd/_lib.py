@@ -134,6 +134,9 @@ def _load():
         f.restype, f.argtypes = i32, [ctypes.c_int32, pp, ctypes.POINTER(Options),
                                       ctypes.POINTER(ctypes.c_void_p)]
     lib.rotseq_batch_execute.restype, lib.rotseq_batch_execute.argtypes = i32, [vp, vp]
+    for name in ("rotseq_batch_update_d", "rotseq_batch_update_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, [vp, ctypes.c_int32, pp]
     lib.rotseq_batch_tune.restype, lib.rotseq_batch_tune.argtypes = i32, [vp, vp, ctypes.c_int32]
     lib.rotseq_batch_info_get.restype = i32
     lib.rotseq_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
@@ -341,6 +344,17 @@ class Batch:
         rc = _load().rotseq_batch_execute(self._handle, _stream(stream))
         if rc != 0:
             raise RotseqError(rc, "batch_execute")
+
+    def update(self, items):
+        """Point the plan at other tensors of the same shapes, in the same
+        order (rotseq_batch_update_*); synchronizes the device."""
+        arr, dbl = _problems(items)
+        lib = _load()
+        fn = lib.rotseq_batch_update_d if dbl else lib.rotseq_batch_update_s
+        rc = fn(self._handle, len(items), arr)
+        if rc != 0:
+            raise RotseqError(rc, "batch_update")
+        self._keep = list(items)
 
     def tune(self, reps=3, stream=None):
         rc = _load().rotseq_batch_tune(self._handle, _stream(stream), int(reps))

@@ -129,6 +129,9 @@ struct rotseq_batch {
     int cus = 0;
     int64_t waves_total = 0;
     double flops = 0.0, bytes = 0.0;
+    int esize = 8;
+    std::vector<int64_t> shapes;  // m, n, k of every caller entry, in caller order
+    std::vector<int> order;       // caller index of each item (dispatch order)
 };
 
 namespace rotseq {
@@ -155,14 +158,13 @@ int set_waves(rotseq_batch *b, int waves)
     return ROTSEQ_SUCCESS;
 }
 
-int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_opts *opts,
-           rotseq_batch **out)
+// Entry checks shared by create and update: every entry as rotseq_d checks
+// it, then pairwise overlap of the A ranges of the entries with work.
+// Returns 0 or -(1000*(idx+1) + argpos); fills `work` with the indices of
+// the entries that have work.
+int check_entries(int32_t count, const std::vector<Entry> &in, int esize, std::vector<int> &work)
 {
-    if (out == nullptr)
-        return -4;
-    *out = nullptr;
-    // Argument checks, entry by entry, then pairwise overlap of the A ranges.
-    std::vector<int> work;
+    work.clear();
     for (int32_t i = 0; i < count; ++i) {
         const Entry &e = in[i];
         const int bad = check_problem(e.m, e.n, e.k, e.A, e.lda, e.C, e.ldc, e.S, e.lds);
@@ -171,19 +173,30 @@ int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_
         if (e.m > 0 && e.n > 1 && e.k > 0)
             work.push_back(i);
     }
-    {
-        std::vector<std::pair<uintptr_t, int>> starts;
-        for (int i : work)
-            starts.emplace_back((uintptr_t)in[i].A, i);
-        std::sort(starts.begin(), starts.end());
-        for (size_t j = 1; j < starts.size(); ++j) {
-            const Entry &prev = in[starts[j - 1].second];
-            const uintptr_t prev_end =
-                starts[j - 1].first + (uintptr_t)esize * (uintptr_t)(prev.lda * (prev.n - 1) + prev.m);
-            if (starts[j].first < prev_end)
-                return -(1000 * (std::max(starts[j].second, starts[j - 1].second) + 1) + 4);
-        }
+    std::vector<std::pair<uintptr_t, int>> starts;
+    for (int i : work)
+        starts.emplace_back((uintptr_t)in[i].A, i);
+    std::sort(starts.begin(), starts.end());
+    for (size_t j = 1; j < starts.size(); ++j) {
+        const Entry &prev = in[starts[j - 1].second];
+        const uintptr_t prev_end =
+            starts[j - 1].first + (uintptr_t)esize * (uintptr_t)(prev.lda * (prev.n - 1) + prev.m);
+        if (starts[j].first < prev_end)
+            return -(1000 * (std::max(starts[j].second, starts[j - 1].second) + 1) + 4);
     }
+    return 0;
+}
+
+int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_opts *opts,
+           rotseq_batch **out)
+{
+    if (out == nullptr)
+        return -4;
+    *out = nullptr;
+    std::vector<int> work;
+    const int bad = check_entries(count, in, esize, work);
+    if (bad)
+        return bad;
     int arith = 0, band = 0, kernel = 0;
     if (!resolve_opts(opts, arith, band, kernel))
         return ROTSEQ_E_UNSUPPORTED;
@@ -220,6 +233,13 @@ int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_
             return ROTSEQ_E_UNSUPPORTED;
         }
     }
+    b->esize = esize;
+    for (int32_t i = 0; i < count; ++i) {
+        b->shapes.push_back(in[i].m);
+        b->shapes.push_back(in[i].n);
+        b->shapes.push_back(in[i].k);
+    }
+    b->order = work;
     std::vector<BatchEntry> ordered;
     for (int i : work) {
         const Entry &e = in[i];
@@ -290,6 +310,63 @@ int create_typed(int32_t count, const P *probs, const rotseq_opts *opts, rotseq_
     return create(count, in, esize, opts, out);
 }
 
+// New A, C and S pointers (and leading dimensions) for an existing plan:
+// the same entries, in the order given at creation, with the same shapes.
+int update(rotseq_batch *b, int32_t count, const std::vector<Entry> &in, int esize)
+{
+    if (b == nullptr)
+        return -1;
+    if (esize != b->esize || (size_t)count * 3 != b->shapes.size())
+        return -2;
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t *sh = &b->shapes[(size_t)i * 3];
+        if (in[i].m != sh[0])
+            return -(1000 * (i + 1) + 1);
+        if (in[i].n != sh[1])
+            return -(1000 * (i + 1) + 2);
+        if (in[i].k != sh[2])
+            return -(1000 * (i + 1) + 3);
+    }
+    std::vector<int> work;
+    const int bad = check_entries(count, in, esize, work);
+    if (bad)
+        return bad;
+    std::vector<BatchItem> items = b->items;
+    for (size_t t = 0; t < items.size(); ++t) {
+        const Entry &e = in[b->order[t]];
+        BatchItem &it = items[t];
+        it.A = e.A;
+        it.C = e.C;
+        it.S = e.S;
+        it.lda = e.lda;
+        it.ldc = e.ldc;
+        it.lds = e.lds;
+    }
+    if (items.empty())
+        return ROTSEQ_SUCCESS;
+    // The table is read by every execution, so none may be in flight.
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(b->dmem, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) !=
+            hipSuccess)
+        return ROTSEQ_E_HIP;
+    b->items.swap(items);
+    return ROTSEQ_SUCCESS;
+}
+
+template <typename P>
+int update_typed(rotseq_batch *b, int32_t count, const P *probs, int esize)
+{
+    if (b == nullptr)
+        return -1;
+    if (count < 0 || (count > 0 && probs == nullptr))
+        return -2;
+    std::vector<Entry> in;
+    in.reserve(count);
+    for (int32_t i = 0; i < count; ++i)
+        in.push_back(entry_of(probs[i]));
+    return update(b, count, in, esize);
+}
+
 template <typename P>
 int one_shot(int32_t count, const P *probs, hipStream_t stream, int esize)
 {
@@ -325,6 +402,16 @@ int rotseq_batch_create_s(int32_t count, const rotseq_problem_s *probs, const ro
 }
 
 int rotseq_batch_execute(rotseq_batch *batch, hipStream_t stream) { return execute(batch, stream); }
+
+int rotseq_batch_update_d(rotseq_batch *batch, int32_t count, const rotseq_problem_d *probs)
+{
+    return update_typed(batch, count, probs, 8);
+}
+
+int rotseq_batch_update_s(rotseq_batch *batch, int32_t count, const rotseq_problem_s *probs)
+{
+    return update_typed(batch, count, probs, 4);
+}
 
 int rotseq_batch_tune(rotseq_batch *b, hipStream_t stream, int32_t reps)
 {

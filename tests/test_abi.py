@@ -124,6 +124,8 @@ def test_batch_detects_overlapping_matrices():
 
 def test_batch_null_handles_are_rejected():
     lib = rs._lib._load()
+    assert lib.rotseq_batch_update_d(None, 0, None) == -1
+    assert lib.rotseq_batch_update_s(None, 0, None) == -1
     assert lib.rotseq_batch_execute(None, None) == -1
     assert lib.rotseq_batch_tune(None, None, 3) == -1
     assert lib.rotseq_batch_info_get(None, None) == -1

@@ -186,3 +186,51 @@ def test_uneven_512_batch_sampled():
             rows = np.sort(rng.choice(pb.m, min(pb.m, 8), replace=False))
             ref = oracle_rows(pb.A, pb.C, pb.S, rows, "f64")
             assert relerr(got[rows], ref, np.asarray(pb.A)[rows]) <= TOL["f64"]
+
+
+def test_batch_update_pointers():
+    """rotseq_batch_update_*: the plan runs on other buffers of the same
+    shapes (other leading dimensions too), eagerly and from a captured graph;
+    a shape change is refused and leaves the plan as it was."""
+    import torch
+    say("batch pointer update")
+    pbs1 = mixed_problems(seed=150)
+    pbs2 = [make_problem(p.m, p.n, p.k, seed=300 + i, lda=max(1, p.m) + (i % 3))
+            for i, p in enumerate(pbs1)]
+    dev1, dev2 = upload(pbs1, "f64"), upload(pbs2, "f64")
+    b = rs.Batch(dev1)
+    b.execute()
+    b.update(dev2)
+    b.execute()
+    torch.cuda.synchronize()
+    check_status()
+    for pb, (A, _, _) in zip(pbs1, dev1):
+        assert relerr(rs.host_colmajor(A), oracle_full(pb, "f64"), pb.A) <= TOL["f64"]
+    for pb, (A, _, _) in zip(pbs2, dev2):
+        assert relerr(rs.host_colmajor(A), oracle_full(pb, "f64"), pb.A) <= TOL["f64"]
+    # a different k for entry 3 is refused with its index and argument
+    bad = list(dev2)
+    A3, C3, S3 = bad[3]
+    bad[3] = (A3, C3[:, :max(1, C3.shape[1] - 1)].contiguous(), S3[:, :max(1, S3.shape[1] - 1)].contiguous())
+    with pytest.raises(rs.RotseqError) as e:
+        b.update(bad)
+    assert e.value.code == -(1000 * 4 + 3)
+    # graph captured on dev2's pointers, then updated back to dev1: replays use dev1
+    dev3 = upload(pbs1, "f64")
+    b.update(dev3)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            b.execute(stream=s)
+    torch.cuda.synchronize()
+    dev4 = upload(pbs2, "f64")
+    b.update(dev4)
+    g.replay()
+    torch.cuda.synchronize()
+    check_status()
+    for pb, (A, _, _) in zip(pbs2, dev4):
+        assert relerr(rs.host_colmajor(A), oracle_full(pb, "f64"), pb.A) <= TOL["f64"]
+    for pb, (A, _, _) in zip(pbs1, dev3):  # untouched by the replay after the update
+        assert np.array_equal(rs.host_colmajor(A), np.asarray(pb.A))
+    b.close()
