@@ -290,10 +290,13 @@ def bench_served(args):
                 delay = arrivals[i] - (time.perf_counter() - t_start)
                 if delay > 0:
                     time.sleep(delay)
-                off = int(r["seed"].generate_state(1)[0]) % (len(theta) - span - 1)
+                state = r["seed"].generate_state(r["sweeps"] + 1)
+                off = int(state[0]) % (len(theta) - span - 1)
                 try:
                     mid = srv.open(a_pool[:n, :n])
                     for sw in range(r["sweeps"]):
+                        if args.k_per_sweep:  # the other reading: k drawn per sweep
+                            k = int(wl["ks"][int(state[sw + 1]) % len(wl["ks"])])
                         o = (off + sw * 7919 * k) % (len(theta) - span - 1)
                         C = c_pool[o:o + (n - 1) * k].reshape((n - 1, k), order="F")
                         S = s_pool[o:o + (n - 1) * k].reshape((n - 1, k), order="F")
@@ -342,13 +345,15 @@ def bench_served(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (Poisson arrivals; n log-uniform [128,4096], m=n; k per request in "
-                "{16,32,64,128}; A = windows of an N(0,1) pool, angles = windows of a U[0,2pi) "
-                "pool; seeded PCG64)",
+        "data": "synthetic (Poisson arrivals; n log-uniform [128,4096], m=n; k per "
+                + ("sweep" if args.k_per_sweep else "request")
+                + " in {16,32,64,128}; A = windows of an N(0,1) pool, angles = windows of a "
+                  "U[0,2pi) pool; seeded PCG64)",
         "config": {"workload": args.workload, "requests": len(reqs),
                    "sweeps_per_request": wl["sweeps"],
                    "offered_requests_per_s": round(rate, 3), "load_vs_saturation": wl["load"],
-                   "budget_bytes": wl["budget"], "k_per": "request", "parallelism": "single GPU"},
+                   "budget_bytes": wl["budget"],
+                   "k_per": "sweep" if args.k_per_sweep else "request", "parallelism": "single GPU"},
         "served": {
             "wall_s": round(wall, 3),
             "sweeps_per_s": round(sweeps / wall, 2),
@@ -380,6 +385,8 @@ def main():
                          "reference for scaling HBM byte counters")
     ap.add_argument("--requests", type=int, default=2000,
                     help="served workload: requests in the open-loop run")
+    ap.add_argument("--k-per-sweep", action="store_true",
+                    help="served workload: draw k for every sweep instead of once per request")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
