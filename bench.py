@@ -83,6 +83,18 @@ def measured_traffic(workload, launch_bytes_alg):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pb, dtype, target_s=15.0):
     """The oracle (threaded over rows) on a bounded sample of rows."""
     import numpy as np
@@ -117,7 +129,8 @@ def cpu_baseline(pb, dtype, target_s=15.0):
     gf = 6.0 * rows * (n - 1) * k / dt / 1e9
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} of {m} rows x all {n} columns x all {k} sequences "
-                      f"({dt:.1f} s, FP64 oracle, row-partitioned threads)"}
+                      f"({dt:.1f} s, FP64 oracle, row-partitioned threads)",
+            "cpu": cpu_model()}
 
 
 def cpu_baseline_variant(pb, variant, target_s=8.0):
@@ -150,7 +163,8 @@ def cpu_baseline_variant(pb, variant, target_s=8.0):
     gf = 6.0 * cnt * r * k / dt / 1e9
     what = f"{cnt} of {n} columns x all {m} rows" if left else f"{cnt} of {m} rows x all {n} columns"
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what} x all {k} sequences ({dt:.1f} s, FP64 oracle, one thread)"}
+            "sample": f"{what} x all {k} sequences ({dt:.1f} s, FP64 oracle, one thread)",
+            "cpu": cpu_model()}
 
 
 def bench_batched(args):
