@@ -97,6 +97,19 @@ def _create(probs, count=None):
     return lib.rotseq_batch_create_d(n, arr if probs else None, None, ctypes.byref(h))
 
 
+@pytest.mark.parametrize("opts", [{"inverse": 1}, {"left": 1}, {"kernel": 1}, {"band": 5},
+                                  {"arith": 9}])
+def test_batch_refuses_unsupported_options(opts):
+    """Batches support the forward right application with the chain kernel
+    only; the refusal comes before any device call."""
+    lib = rs._lib._load()
+    base = 0x10000000
+    probs = [_problem(8, 10, 4, base + i * 0x100000) for i in range(3)]
+    arr = (rs.Problem * 3)(*probs)
+    h = ctypes.c_void_p()
+    assert lib.rotseq_batch_create_d(3, arr, rs._lib._opts(opts), ctypes.byref(h)) == 4
+
+
 def test_batch_rejects_bad_count_and_null_array():
     assert _create([], count=-1) == -1
     assert _create([], count=3) == -2
