@@ -28,7 +28,10 @@
  * closed form and bitwise agreement with the right application on A^T; the
  * reflector sequences by dense products of I - tau v v^T (orthogonal and
  * arbitrary tau), annihilation of a row into its last entry, the tau = 0 and
- * (tau, nu) = (2, 0) closed forms, norm invariance and a round trip.
+ * (tau, nu) = (2, 0) closed forms, norm invariance and a round trip; the
+ * 3x3 reflector sequences by dense products, a norm transfer into entry n-2,
+ * the tau = 0 and (tau, nu1, nu2) = (2, 0, 0) closed forms, bitwise agreement
+ * with the 2x2 reflectors when nu2 = 0, and row-norm invariance.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -244,4 +247,35 @@ void oracle_reflseq_left_d(int64_t m, int64_t n, int64_t k,
     for (int64_t p = 0; p < k; ++p)
         for (int64_t j = 0; j + 1 < m; ++j)
             refl(n, &A[j], &A[j + 1], lda, TAU[j + p * ldt], NU[j + p * ldn]);
+}
+
+/*
+ * Sequences of 3x3 reflectors, the double-shift QR case of Section 9 (the
+ * paper's outlook).  Reflector (j, p) mixes columns j, j+1, j+2:
+ *   H(j,p) = I - tau v v^T,  v = e_j + nu1 e_{j+1} + nu2 e_{j+2},
+ *   tau = TAU(j,p), nu1 = NU1(j,p), nu2 = NU2(j,p); TAU, NU1, NU2 are
+ *   (n-2) x k with leading dimensions ldt, ld1, ld2.
+ * Per row, with (x, y, z) = (A(i,j), A(i,j+1), A(i,j+2)):
+ *   w = x + nu1*y + nu2*z;  x -= tau*w;  y -= (tau*nu1)*w;  z -= (tau*nu2)*w.
+ * In the order of Algorithm 2: for p = 0..k-1, for j = 0..n-3;
+ * A <- A H(0,0) H(1,0) ... H(n-3,k-1).
+ */
+void oracle_refl3seq_d(int64_t m, int64_t n, int64_t k,
+                       double *A, int64_t lda,
+                       const double *TAU, int64_t ldt,
+                       const double *NU1, int64_t ld1,
+                       const double *NU2, int64_t ld2)
+{
+    for (int64_t p = 0; p < k; ++p)
+        for (int64_t j = 0; j + 2 < n; ++j) {
+            double tau = TAU[j + p * ldt], nu1 = NU1[j + p * ld1], nu2 = NU2[j + p * ld2];
+            double t1 = tau * nu1, t2 = tau * nu2;
+            double *x = &A[j * lda], *y = &A[(j + 1) * lda], *z = &A[(j + 2) * lda];
+            for (int64_t i = 0; i < m; ++i) {
+                double w = x[i] + nu1 * y[i] + nu2 * z[i];
+                x[i] = x[i] - tau * w;
+                y[i] = y[i] - t1 * w;
+                z[i] = z[i] - t2 * w;
+            }
+        }
 }

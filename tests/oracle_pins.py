@@ -490,3 +490,114 @@ def pin_refl_closed_forms(apply_refl):
 
 
 REFL_PINS = [pin_refl_dense, pin_refl_norm_transfer, pin_refl_closed_forms]
+
+
+# ---------------------------------------------------------------------------
+# Sequences of 3x3 reflectors (the double-shift QR case named in Section 9).
+# Reflector (j, p) is I - tau v v^T with v = e_j + nu1 e_{j+1} + nu2 e_{j+2};
+# apply_refl3(A, TAU, NU1, NU2) applies A <- A H(0,0) ... H(n-3,k-1) in place.
+
+def dense_h3(TAU, NU1, NU2, n):
+    """Product H(0,0) H(1,0) ... H(n-3,k-1) as a dense n x n matrix."""
+    H = np.eye(n)
+    for p in range(TAU.shape[1]):
+        for j in range(n - 2):
+            v = np.zeros(n)
+            v[j], v[j + 1], v[j + 2] = 1.0, NU1[j, p], NU2[j, p]
+            H = H @ (np.eye(n) - TAU[j, p] * np.outer(v, v))
+    return H
+
+
+def orthogonal_reflectors3(rng, r, k):
+    """Orthogonal 3x3 reflectors: tau = 2 / (1 + nu1^2 + nu2^2), 10% tau = 0."""
+    nu1, nu2 = rng.standard_normal((r, k)), rng.standard_normal((r, k))
+    tau = 2.0 / (1.0 + nu1 * nu1 + nu2 * nu2)
+    tau[rng.random((r, k)) < 0.1] = 0.0
+    return tau, nu1, nu2
+
+
+def pin_refl3_dense(apply_refl3):
+    """R3-1: A H(0,0)...H(n-3,k-1) against the dense product, for orthogonal
+    and for arbitrary (tau, nu1, nu2), with padded leading dimensions."""
+    rng = np.random.Generator(np.random.PCG64(311))
+    for idx, (m, n, k) in enumerate([(1, 3, 1), (4, 3, 2), (5, 4, 3), (3, 7, 4), (6, 10, 2)]):
+        for ortho in (True, False):
+            if ortho:
+                tau, nu1, nu2 = orthogonal_reflectors3(rng, n - 2, k)
+            else:
+                tau = rng.uniform(-0.5, 2.5, (n - 2, k))
+                nu1, nu2 = rng.standard_normal((n - 2, k)), rng.standard_normal((n - 2, k))
+            A0 = rng.standard_normal((m, n))
+            A = colmajor(A0, m + idx % 2)
+            pad = _padding(A)
+            apply_refl3(A, colmajor(tau, n - 2 + idx % 3), colmajor(nu1, n - 1), colmajor(nu2))
+            e = relerr(A, A0 @ dense_h3(tau, nu1, nu2, n))
+            assert e <= 1e-13, f"3x3 reflectors vs dense m={m} n={n} k={k} ortho={ortho}: {e:.3e}"
+            assert np.array_equal(_padding(A), pad), "padding rows of A were modified"
+
+
+def pin_refl3_norm_transfer(apply_refl3):
+    """R3-2: reflectors built from the row push its whole norm into entry
+    n-2.  A Householder reflector maps x = (a, b, c) to y = (0, -sign(b) r, 0),
+    r = |x|, when v is proportional to x - y: v = (1, (b + sign(b) r)/a, c/a)
+    and tau = 2 / v^T v.  The next window starts with the entry just written,
+    so a stays nonzero; the final row is zero except entry n-2 = +-|row|."""
+    rng = np.random.Generator(np.random.PCG64(312))
+    n = 11
+    row = rng.standard_normal(n)
+    tau, nu1, nu2 = np.zeros((n - 2, 1)), np.zeros((n - 2, 1)), np.zeros((n - 2, 1))
+    x = row.copy()
+    for j in range(n - 2):
+        a, b, c = x[j], x[j + 1], x[j + 2]
+        r = math.sqrt(a * a + b * b + c * c)
+        v1, v2 = (b + math.copysign(r, b)) / a, c / a
+        tau[j, 0], nu1[j, 0], nu2[j, 0] = 2.0 / (1.0 + v1 * v1 + v2 * v2), v1, v2
+        x[j], x[j + 1], x[j + 2] = 0.0, -math.copysign(r, b), 0.0
+    A = colmajor(row[None, :])
+    apply_refl3(A, colmajor(tau), colmajor(nu1), colmajor(nu2))
+    out = np.asarray(A)[0]
+    nrm = float(np.linalg.norm(row))
+    rest = np.delete(out, n - 2)
+    assert np.max(np.abs(rest)) <= 40 * n * U * nrm, f"entries not annihilated: {rest}"
+    assert abs(out[n - 2] - x[n - 2]) <= 40 * n * U * nrm, f"entry n-2 {out[n - 2]} != {x[n - 2]}"
+    assert abs(abs(x[n - 2]) - nrm) <= 40 * n * U * nrm
+
+
+def pin_refl3_closed_forms(apply_refl3, apply_refl2):
+    """R3-3: tau = 0 is the identity (bitwise); (tau, nu1, nu2) = (2, 0, 0) is
+    diag(-1, 1, 1) on the window, so k sequences multiply columns 0..n-3 by
+    (-1)^k (exact); nu2 = 0 is the 2x2 reflector (tau, nu1) on columns j, j+1
+    with the same roundings, so it equals the 2x2 sequence whose last
+    reflector is the identity; orthogonal reflectors keep row norms."""
+    rng = np.random.Generator(np.random.PCG64(313))
+    m, n, k = 4, 7, 3
+    A0 = rng.standard_normal((m, n))
+    A = colmajor(A0)
+    apply_refl3(A, colmajor(np.zeros((n - 2, k))), colmajor(rng.standard_normal((n - 2, k))),
+                colmajor(rng.standard_normal((n - 2, k))))
+    assert np.array_equal(np.asarray(A), A0), "tau = 0 changed A"
+    A = colmajor(A0)
+    apply_refl3(A, colmajor(np.full((n - 2, k), 2.0)), colmajor(np.zeros((n - 2, k))),
+                colmajor(np.zeros((n - 2, k))))
+    ref = A0.copy()
+    ref[:, :-2] *= (-1.0) ** k
+    assert np.array_equal(np.asarray(A), ref), "(tau, nu1, nu2) = (2, 0, 0) closed form"
+    m, n, k = 5, 9, 4
+    tau, nu1, _ = orthogonal_reflectors3(rng, n - 2, k)
+    A0 = rng.standard_normal((m, n))
+    A = colmajor(A0)
+    apply_refl3(A, colmajor(tau), colmajor(nu1), colmajor(np.zeros((n - 2, k))))
+    B = colmajor(A0)
+    apply_refl2(B, colmajor(np.vstack([tau, np.zeros((1, k))])), colmajor(np.vstack([nu1, np.zeros((1, k))])))
+    assert np.array_equal(np.asarray(A), np.asarray(B)), "nu2 = 0 differs from the 2x2 reflectors"
+    m, n, k = 9, 23, 8
+    tau, nu1, nu2 = orthogonal_reflectors3(rng, n - 2, k)
+    A0 = rng.standard_normal((m, n))
+    A = colmajor(A0)
+    apply_refl3(A, colmajor(tau), colmajor(nu1), colmajor(nu2))
+    dev = np.max(np.abs(np.linalg.norm(np.asarray(A), axis=1) / np.linalg.norm(A0, axis=1) - 1))
+    assert dev <= 40 * U * (n - 2) * k, f"row norm deviation {dev:.3e}"
+    assert relerr(np.asarray(A), A0) > 1e-3
+
+
+REFL3_PINS = [pin_refl3_dense, pin_refl3_norm_transfer]

@@ -11,7 +11,8 @@ import pytest
 
 import oracle
 from oracle import build as obuild
-from oracle_pins import ALL_PINS, LEFT_PINS, REFL_PINS, pin_left_is_right_on_transpose
+from oracle_pins import (ALL_PINS, LEFT_PINS, REFL3_PINS, REFL_PINS, pin_left_is_right_on_transpose,
+                         pin_refl3_closed_forms)
 
 FWD_LOOP = ("    for (int64_t p = 0; p < k; ++p)\n"
             "        for (int64_t j = 0; j + 1 < n; ++j)\n"
@@ -78,6 +79,21 @@ REFL_MUTANTS = {
                                    "        for (int64_t j = 0; j + 1 < n; ++j)\n"
                                    "            refl("),
     "refl_left_wrong_stride": ("refl(n, &A[j], &A[j + 1], lda,", "refl(n, &A[j], &A[j + 1], 1,"),
+}
+
+
+# Mutants of the 3x3 reflector sequence, caught by the 3x3 reflector pins.
+REFL3_LOAD = "double tau = TAU[j + p * ldt], nu1 = NU1[j + p * ld1], nu2 = NU2[j + p * ld2];"
+REFL3_MUTANTS = {
+    "refl3_w_drops_nu2": ("double w = x[i] + nu1 * y[i] + nu2 * z[i];", "double w = x[i] + nu1 * y[i];"),
+    "refl3_z_uses_t1": ("z[i] = z[i] - t2 * w;", "z[i] = z[i] - t1 * w;"),
+    "refl3_x_sign": ("x[i] = x[i] - tau * w;", "x[i] = x[i] + tau * w;"),
+    "refl3_t2_uses_nu1": ("double t1 = tau * nu1, t2 = tau * nu2;", "double t1 = tau * nu1, t2 = tau * nu1;"),
+    "refl3_nu_swapped": (REFL3_LOAD, "double tau = TAU[j + p * ldt], nu1 = NU2[j + p * ld2], nu2 = NU1[j + p * ld1];"),
+    "refl3_window_overlaps": ("*z = &A[(j + 2) * lda];", "*z = &A[(j + 1) * lda];"),
+    "refl3_last_reflector_dropped": ("for (int64_t j = 0; j + 2 < n; ++j) {", "for (int64_t j = 0; j + 3 < n; ++j) {"),
+    "refl3_loops_swapped": ("    for (int64_t p = 0; p < k; ++p)\n        for (int64_t j = 0; j + 2 < n; ++j) {",
+                            "    for (int64_t j = 0; j + 2 < n; ++j)\n        for (int64_t p = 0; p < k; ++p) {"),
 }
 
 
@@ -153,3 +169,21 @@ def test_refl_mutant_is_caught(name, source, tmp_path):
         oracle.reflseq(A, TAU, NU, inverse=inverse, left=left, lib=lib)
 
     assert _fails_some(REFL_PINS, refl), f"mutant {name} passed every reflector pin"
+
+
+@pytest.mark.parametrize("name", sorted(REFL3_MUTANTS))
+def test_refl3_mutant_is_caught(name, source, tmp_path):
+    lib = _mutant_lib(source, tmp_path, *REFL3_MUTANTS[name], name)
+
+    def refl3(A, TAU, NU1, NU2):
+        oracle.refl3seq(A, TAU, NU1, NU2, lib=lib)
+
+    def refl2(A, TAU, NU):
+        oracle.reflseq(A, TAU, NU, lib=lib)
+
+    failed = _fails_some(REFL3_PINS, refl3)
+    try:
+        pin_refl3_closed_forms(refl3, refl2)
+    except AssertionError as e:
+        failed.append(("pin_refl3_closed_forms", str(e)[:80]))
+    assert failed, f"mutant {name} passed every 3x3 reflector pin"

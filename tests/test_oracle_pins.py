@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle_pins import (ALL_PINS, LEFT_PINS, REFL_PINS, colmajor, pin_left_is_right_on_transpose,
-                         rand_problem)
+from oracle_pins import (ALL_PINS, LEFT_PINS, REFL3_PINS, REFL_PINS, colmajor, pin_left_is_right_on_transpose,
+                         pin_refl3_closed_forms, rand_problem)
 
 
 def oracle_apply(A, C, S, inverse=False):
@@ -64,3 +64,26 @@ def test_left_is_right_on_transpose():
 @pytest.mark.parametrize("pin", REFL_PINS, ids=lambda p: p.__name__)
 def test_refl_pin(pin):
     pin(oracle_refl)
+
+
+def oracle_refl3(A, TAU, NU1, NU2):
+    oracle.refl3seq(A, TAU, NU1, NU2)
+
+
+@pytest.mark.parametrize("pin", REFL3_PINS, ids=lambda p: p.__name__)
+def test_refl3_pin(pin):
+    pin(oracle_refl3)
+
+
+def test_refl3_closed_forms():
+    pin_refl3_closed_forms(oracle_refl3, oracle_refl)
+
+
+def test_refl3_quick_returns():
+    """n <= 2 and k = 0 leave A alone; mismatched coefficient shapes raise."""
+    A = colmajor(np.arange(6.0).reshape(3, 2))
+    oracle.refl3seq(A, colmajor(np.zeros((0, 2))), colmajor(np.zeros((0, 2))), colmajor(np.zeros((0, 2))))
+    assert np.array_equal(np.asarray(A), np.arange(6.0).reshape(3, 2))
+    with pytest.raises(ValueError):
+        oracle.refl3seq(colmajor(np.zeros((2, 5))), colmajor(np.zeros((3, 1))), colmajor(np.zeros((3, 2))),
+                        colmajor(np.zeros((3, 1))))
