@@ -41,6 +41,9 @@ WORKLOADS = {
     "left-f64-10240-k192": dict(m=10240, n=10240, k=192, dtype="f64", seed=2, variant="left"),
     # 2x2 reflectors (tau, nu) in place of (c, s)
     "refl-f64-10240-k192": dict(m=10240, n=10240, k=192, dtype="f64", seed=2, variant="refl"),
+    # 3x3 reflectors (tau, nu1, nu2) on columns j, j+1, j+2
+    "refl3-f64-10240-k192": dict(m=10240, n=10240, k=192, dtype="f64", seed=2, variant="refl3"),
+    "refl3-f32-10240-k192": dict(m=10240, n=10240, k=192, dtype="f32", seed=2, variant="refl3"),
 }
 BATCHED = {"batched-f64-512": dict(count=512, seed=4, dtype="f64")}
 SERVED = {"served-f64": dict(seed=5, n_lo=128, n_hi=4096, sweeps=20, ks=(16, 32, 64, 128),
@@ -140,7 +143,10 @@ def cpu_baseline_variant(pb, variant, target_s=8.0):
     import numpy as np
     import oracle
     A = np.asarray(pb.A)
-    C, S = oracle.colmajor(np.asarray(pb.C)), oracle.colmajor(np.asarray(pb.S))
+    if variant == "refl3":
+        coef = [oracle.colmajor(np.asarray(X)) for X in (pb.TAU, pb.NU1, pb.NU2)]
+    else:
+        C, S = oracle.colmajor(np.asarray(pb.C)), oracle.colmajor(np.asarray(pb.S))
     m, n, k = pb.m, pb.n, pb.k
     left = variant == "left"
     total = n if left else m
@@ -150,6 +156,8 @@ def cpu_baseline_variant(pb, variant, target_s=8.0):
         t0 = time.perf_counter()
         if left:
             oracle.rotseq(sub, C, S, left=True)
+        elif variant == "refl3":
+            oracle.refl3seq(sub, *coef)
         else:
             oracle.reflseq(sub, C, S)
         return time.perf_counter() - t0
@@ -159,8 +167,8 @@ def cpu_baseline_variant(pb, variant, target_s=8.0):
     while dt < 0.5 * target_s and cnt < total:
         cnt = int(min(total, max(2 * cnt, cnt * target_s / max(dt, 1e-3))))
         dt = timed(cnt)
-    r = (m - 1) if left else (n - 1)
-    gf = 6.0 * cnt * r * k / dt / 1e9
+    r = (m - 1) if left else (n - 2) if variant == "refl3" else (n - 1)
+    gf = (10.0 if variant == "refl3" else 6.0) * cnt * r * k / dt / 1e9
     what = f"{cnt} of {n} columns x all {m} rows" if left else f"{cnt} of {m} rows x all {n} columns"
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
             "sample": f"{what} x all {k} sequences ({dt:.1f} s, FP64 oracle, one thread)",
@@ -427,23 +435,33 @@ def main():
     import numpy as np
     import torch
     import paper_2412_01852_amd as rs
-    from paper_2412_01852_amd.inputs import make_left_problem, make_problem, make_refl_problem
+    from paper_2412_01852_amd.inputs import (make_left_problem, make_problem, make_refl3_problem,
+                                             make_refl_problem)
 
     wl = WORKLOADS[args.workload]
     m, n, k, dtype = wl["m"], wl["n"], wl["k"], wl["dtype"]
     variant = wl.get("variant", "right")
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    make = {"right": make_problem, "left": make_left_problem, "refl": make_refl_problem}[variant]
+    make = {"right": make_problem, "left": make_left_problem, "refl": make_refl_problem,
+            "refl3": make_refl3_problem}[variant]
     pb = make(m, n, k, seed=wl["seed"])
     A = rs.device_colmajor(pb.A, "cuda:0", tdt)
-    C = rs.device_colmajor(pb.C, "cuda:0", tdt)
-    S = rs.device_colmajor(pb.S, "cuda:0", tdt)
-    # counted work: 6 flops per (rotation or reflector, entry it updates)
-    flops = 6.0 * (n * (m - 1) if variant == "left" else m * (n - 1)) * k
     esize = 8 if dtype == "f64" else 4
-    nrot = (m - 1) if variant == "left" else (n - 1)
-    alg_bytes = esize * (2.0 * m * n + 2.0 * nrot * k)
-    if variant == "right":
+    if variant == "refl3":
+        TAU, NU1, NU2 = (rs.device_colmajor(X, "cuda:0", tdt) for X in (pb.TAU, pb.NU1, pb.NU2))
+        # counted work: 10 flops per (reflector, row); coefficients read once
+        flops = 10.0 * m * (n - 2) * k
+        alg_bytes = esize * (2.0 * m * n + 3.0 * (n - 2) * k)
+    else:
+        C = rs.device_colmajor(pb.C, "cuda:0", tdt)
+        S = rs.device_colmajor(pb.S, "cuda:0", tdt)
+        # counted work: 6 flops per (rotation or reflector, entry it updates)
+        flops = 6.0 * (n * (m - 1) if variant == "left" else m * (n - 1)) * k
+        nrot = (m - 1) if variant == "left" else (n - 1)
+        alg_bytes = esize * (2.0 * m * n + 2.0 * nrot * k)
+    if variant == "refl3":
+        step = lambda: rs.refl3seq(A, TAU, NU1, NU2)  # noqa: E731
+    elif variant == "right":
         step = lambda: rs.rotseq(A, C, S)  # noqa: E731
     elif variant == "left":
         step = lambda: rs.rotseq(A, C, S, opts={"left": 1})  # noqa: E731
@@ -483,13 +501,15 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
-        "data": "synthetic (A iid N(0,1), angles iid U[0,2pi), seeded PCG64)" if variant != "refl"
-                else "synthetic (A iid N(0,1), reflectors nu = tan(phi), phi iid U(-pi/2,pi/2), "
-                     "tau = 2/(1+nu^2), 5% tau = 0; seeded PCG64)",
+        "data": {"refl": "synthetic (A iid N(0,1), reflectors nu = tan(phi), phi iid U(-pi/2,pi/2), "
+                         "tau = 2/(1+nu^2), 5% tau = 0; seeded PCG64)",
+                 "refl3": "synthetic (A iid N(0,1), 3x3 reflectors with plane normal u uniform on "
+                          "the sphere, nu = u[1:]/u[0], tau = 2 u[0]^2, 5% tau = 0; seeded PCG64)"}.get(
+                     variant, "synthetic (A iid N(0,1), angles iid U[0,2pi), seeded PCG64)"),
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "lda": m,
-                   "arith": "lift", "parallelism": "single GPU",
+                   "arith": "fma" if variant == "refl3" else "lift", "parallelism": "single GPU",
                    "sequences_mix": "rows" if variant == "left" else "columns",
-                   "elements": "reflectors" if variant == "refl" else "rotations"},
+                   "elements": {"refl": "reflectors", "refl3": "3x3 reflectors"}.get(variant, "rotations")},
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),

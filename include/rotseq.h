@@ -195,6 +195,40 @@ int rotseq_refl_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
                      void *workspace, size_t ws_bytes);
 
 /*
+ * rotseq_refl3_d / rotseq_refl3_s: sequences of 3x3 reflectors, as the
+ * double-shift variant of the implicit QR algorithm needs (named among the
+ * paper's future work, Section 9).  Reflector (j,p), 0 <= j < n-2, acts on
+ * columns j, j+1, j+2:
+ *     H(j,p) = I - tau v v^T,   v = e_j + nu1 e_{j+1} + nu2 e_{j+2},
+ *     tau = TAU[j + p*ldt],  nu1 = NU1[j + p*ld1],  nu2 = NU2[j + p*ld2],
+ * and the call computes A <- A H(0,0) H(1,0) ... H(n-3,0) H(0,1) ...
+ * H(n-3,k-1).  Per row, with (x, y, z) = (A(i,j), A(i,j+1), A(i,j+2)):
+ *     w = x + nu1*y + nu2*z;  x -= tau*w;  y -= tau*nu1*w;  z -= tau*nu2*w.
+ * The formula is applied as written, so any (tau, nu1, nu2) is accepted
+ * (orthogonal reflectors have tau*(1 + nu1^2 + nu2^2) = 2, or tau = 0).
+ * Arguments: 1 m, 2 n, 3 k (>= 0); 4 A (device, m x n, column-major);
+ * 5 lda >= max(1, m); 6 TAU (device, (n-2) x k); 7 ldt >= max(1, n-2);
+ * 8 NU1, 9 ld1, 10 NU2, 11 ld2 likewise; 12 stream.  Quick return (nothing
+ * launched) when m == 0, n <= 2 or k == 0; device pointers may then be NULL.
+ * 13-14: optional device workspace of at least
+ * rotseq_refl3_workspace_bytes() bytes, 256-byte aligned (NULL: the library
+ * keeps one per device and stream; ROTSEQ_E_WORKSPACE if too small or
+ * misaligned).  ROTSEQ_E_UNSUPPORTED if m > 2^31 - 65 or n > 2^30 - 1.
+ * Only the right application in the forward order is provided.
+ */
+int rotseq_refl3_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
+                   const double *TAU, int64_t ldt, const double *NU1, int64_t ld1,
+                   const double *NU2, int64_t ld2, hipStream_t stream,
+                   void *workspace, size_t ws_bytes);
+int rotseq_refl3_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
+                   const float *TAU, int64_t ldt, const float *NU1, int64_t ld1,
+                   const float *NU2, int64_t ld2, hipStream_t stream,
+                   void *workspace, size_t ws_bytes);
+/* Workspace bytes of rotseq_refl3_{d,s} for this shape (dtype 'd' or 's');
+ * 0 for quick-return shapes.  Host-only. */
+size_t rotseq_refl3_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k);
+
+/*
  * Device workspace bytes needed by rotseq_ex_{d,s} and rotseq_refl_ex_{d,s}
  * for this shape and options; dtype is 'd' or 's'.  Returns 0 for
  * quick-return shapes and for invalid arguments.  Host-only; never touches

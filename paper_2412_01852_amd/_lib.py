@@ -111,6 +111,12 @@ def _load():
     for name in ("rotseq_ex_d", "rotseq_ex_s", "rotseq_refl_ex_d", "rotseq_refl_ex_s"):
         f = getattr(lib, name)
         f.restype, f.argtypes = i32, base + [ctypes.POINTER(Options), vp, ctypes.c_size_t]
+    for name in ("rotseq_refl3_d", "rotseq_refl3_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp,
+                                      ctypes.c_size_t]
+    lib.rotseq_refl3_workspace_bytes.restype = ctypes.c_size_t
+    lib.rotseq_refl3_workspace_bytes.argtypes = [ctypes.c_char, i64, i64, i64]
     lib.rotseq_workspace_bytes.restype = ctypes.c_size_t
     lib.rotseq_workspace_bytes.argtypes = [ctypes.c_char, i64, i64, i64, ctypes.POINTER(Options)]
     lib.rotseq_check_args.restype = i32
@@ -226,6 +232,43 @@ def reflseq(A, TAU, NU, *, opts=None, workspace=None, stream=None):
     v = e_j + nu e_{j+1} (rotseq_refl_ex_*); arguments as for rotseq with
     TAU, NU in place of C, S."""
     return _call(True, A, TAU, NU, opts, workspace, stream)
+
+
+def refl3seq(A, TAU, NU1, NU2, *, workspace=None, stream=None):
+    """A <- A * H(0,0) ... H(n-3,k-1) for 3x3 reflectors H = I - tau v v^T,
+    v = e_j + nu1 e_{j+1} + nu2 e_{j+2} (rotseq_refl3_*).  A: (m, n)
+    float64/float32 column-major device tensor; TAU, NU1, NU2: (n-2, k) of
+    the same dtype.  Returns A."""
+    import torch
+    if A.dtype not in (torch.float64, torch.float32):
+        raise TypeError("A must be float64 or float32")
+    if any(t.dtype != A.dtype for t in (TAU, NU1, NU2)):
+        raise TypeError("A and the coefficient arrays must share a dtype")
+    m, n = A.shape
+    k = TAU.shape[1]
+    if TAU.shape != NU1.shape or TAU.shape != NU2.shape or TAU.shape[0] != max(n - 2, 0):
+        raise ValueError(f"coefficient arrays must be ({max(n - 2, 0)}, k); got "
+                         f"{tuple(TAU.shape)}, {tuple(NU1.shape)}, {tuple(NU2.shape)}")
+    for t, nm in ((A, "A"), (TAU, "TAU"), (NU1, "NU1"), (NU2, "NU2")):
+        if t.numel() and not t.is_cuda:
+            raise ValueError(f"{nm} must be a device tensor")
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    lib = _load()
+    fn = lib.rotseq_refl3_d if A.dtype == torch.float64 else lib.rotseq_refl3_s
+    wptr = workspace.data_ptr() if workspace is not None else None
+    wbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    rc = fn(m, n, k, ptr(A), _ld(A, "A"), ptr(TAU), _ld(TAU, "TAU"), ptr(NU1), _ld(NU1, "NU1"),
+            ptr(NU2), _ld(NU2, "NU2"), ctypes.c_void_p(st.cuda_stream), wptr, wbytes)
+    if rc != 0:
+        raise RotseqError(rc, "refl3seq")
+    return A
+
+
+def refl3_workspace_bytes(dtype, m, n, k):
+    ch = {"float64": b"d", "double": b"d", "d": b"d", "float32": b"s", "float": b"s", "s": b"s"}[
+        str(dtype).replace("torch.", "")]
+    return _load().rotseq_refl3_workspace_bytes(ch, m, n, k)
 
 
 def _call(refl, A, C, S, opts, workspace, stream):

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "rotseq_internal.h"
+#include "rotseq_refl3.h"
 
 namespace rotseq {
 
@@ -449,6 +450,66 @@ int run(int kind, int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C
     return ROTSEQ_SUCCESS;
 }
 
+// Sequences of 3x3 reflectors: arguments checked in the order of
+// rotseq_refl3_d, then the records are prepared and the bands swept.
+template <typename T>
+int run_refl3(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, int64_t ldt,
+              const T *NU1, int64_t ld1, const T *NU2, int64_t ld2, hipStream_t stream, void *ws,
+              size_t ws_bytes)
+{
+    if (m < 0)
+        return -1;
+    if (n < 0)
+        return -2;
+    if (k < 0)
+        return -3;
+    const bool work = m > 0 && n > 2 && k > 0;
+    const int64_t n2 = n > 2 ? n - 2 : 1;
+    if (work && A == nullptr)
+        return -4;
+    if (lda < (m > 1 ? m : 1))
+        return -5;
+    if (work && TAU == nullptr)
+        return -6;
+    if (ldt < n2)
+        return -7;
+    if (work && NU1 == nullptr)
+        return -8;
+    if (ld1 < n2)
+        return -9;
+    if (work && NU2 == nullptr)
+        return -10;
+    if (ld2 < n2)
+        return -11;
+    if (!work)
+        return ROTSEQ_SUCCESS;
+    Refl3Plan p;
+    if (!refl3_plan(p, m, n, k, lda, (int)sizeof(T)))
+        return ROTSEQ_E_UNSUPPORTED;
+    if (ws) {
+        if (ws_bytes < p.total || ((uintptr_t)ws & 255) != 0)
+            return ROTSEQ_E_WORKSPACE;
+    } else {
+        const int rc = pool().get(stream, p.total, &ws);
+        if (rc)
+            return rc;
+    }
+    Profiler::Rec rec{};
+    const bool timed = profiler().begin(rec, stream);
+    if (launch_refl3_prep(p, TAU, ldt, NU1, ld1, NU2, ld2, ws, stream) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (timed)
+        (void)hipEventRecord(rec.e1, stream);
+    if (launch_refl3_sweep(p, A, ws, stream) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (timed) {
+        (void)hipEventRecord(rec.e2, stream);
+        (void)hipEventRecord(rec.e3, stream);
+        profiler().finish(rec);
+    }
+    return ROTSEQ_SUCCESS;
+}
+
 }  // namespace
 
 int check_problem(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda, const void *C,
@@ -528,6 +589,31 @@ int rotseq_refl_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, con
                      const rotseq_opts *opts, void *workspace, size_t ws_bytes)
 {
     return run<float>(kReflect, m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace, ws_bytes);
+}
+
+int rotseq_refl3_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const double *TAU,
+                   int64_t ldt, const double *NU1, int64_t ld1, const double *NU2, int64_t ld2,
+                   hipStream_t stream, void *workspace, size_t ws_bytes)
+{
+    return run_refl3<double>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, workspace,
+                             ws_bytes);
+}
+
+int rotseq_refl3_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, const float *TAU,
+                   int64_t ldt, const float *NU1, int64_t ld1, const float *NU2, int64_t ld2,
+                   hipStream_t stream, void *workspace, size_t ws_bytes)
+{
+    return run_refl3<float>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, workspace,
+                            ws_bytes);
+}
+
+size_t rotseq_refl3_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k)
+{
+    const int esize = dtype == 'd' ? 8 : dtype == 's' ? 4 : 0;
+    Refl3Plan p;
+    if (!esize || !refl3_plan(p, m, n, k, m > 1 ? m : 1, esize))
+        return 0;
+    return p.total;
 }
 
 int rotseq_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const double *C, int64_t ldc,

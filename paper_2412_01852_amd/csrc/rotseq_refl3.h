@@ -1,0 +1,27 @@
+// Internal interface of the 3x3 reflector sweep (rotseq_refl3.hip) for the
+// host runtime.  Not installed; the public interface is include/rotseq.h.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rotseq {
+
+// Sequences of 3x3 reflectors (rotseq_refl3_*): bands of `band` sequences,
+// one wave per band, at most `waves` bands per launch; records of
+// (tau, nu1, nu2) in wavefront order, `steps` local steps per band.
+struct Refl3Plan {
+    int64_t m, n, k, lda;
+    int esize, band, nbands, steps, waves;
+    int64_t rec_elems;  // elements of the record buffer
+    size_t total;       // workspace bytes
+};
+// Fills `p` for a call with work (m > 0, n > 2, k > 0); false if the shape
+// is outside what the kernel indexes with 32-bit integers.  Host-only.
+bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int esize);
+hipError_t launch_refl3_prep(const Refl3Plan &p, const void *TAU, int64_t ldt, const void *NU1,
+                             int64_t ld1, const void *NU2, int64_t ld2, void *ws, hipStream_t stream);
+hipError_t launch_refl3_sweep(const Refl3Plan &p, void *A, const void *ws, hipStream_t stream);
+
+}  // namespace rotseq

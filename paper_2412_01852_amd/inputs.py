@@ -105,6 +105,48 @@ def make_refl_problem(m, n, k, seed=0, *, left=False, lda=None, ldc=None, lds=No
     return Problem(m, n, k, A, TAU, NU)
 
 
+@dataclass
+class Refl3Problem:
+    m: int
+    n: int
+    k: int
+    A: np.ndarray    # (m, n) column-major view, float64
+    TAU: np.ndarray  # (n-2, k) column-major views, float64
+    NU1: np.ndarray
+    NU2: np.ndarray
+
+    @property
+    def flops(self):
+        """Counted work: 10 flops per (reflector, row), 10 m (n-2) k
+        (w = x + nu1 y + nu2 z: 4; x, y, z updates: 2 each)."""
+        return 10 * self.m * max(self.n - 2, 0) * self.k
+
+
+def make_reflectors3(r, k, rng, *, lds=(None, None, None), identity_frac=0.05, pad_fill=np.nan):
+    """(r x k) parameters (tau, nu1, nu2) of orthogonal 3x3 reflectors
+    I - tau v v^T, v = (1, nu1, nu2): the unit normal u of the reflecting
+    plane is uniform on the sphere and v = u / u_0, so tau = 2 u_0^2; a
+    fraction ``identity_frac`` is tau = 0 (identity), as for windows that
+    are already reduced.  ``lds`` are the three leading dimensions."""
+    u = rng.standard_normal(3 * r * k).reshape(3, k, r).transpose(0, 2, 1)
+    u = u / np.linalg.norm(u, axis=0)
+    ident = rng.uniform(0.0, 1.0, r * k).reshape(k, r).T < identity_frac
+    TAU, NU1, NU2 = (_colmajor_buffer(r, k, ld, pad_fill)[1] for ld in lds)
+    NU1[...] = u[1] / u[0]
+    NU2[...] = u[2] / u[0]
+    TAU[...] = np.where(ident, 0.0, 2.0 / (1.0 + NU1 * NU1 + NU2 * NU2))
+    return TAU, NU1, NU2
+
+
+def make_refl3_problem(m, n, k, seed=0, *, lda=None, lds=(None, None, None), pad_fill=np.nan):
+    """3x3 reflector problem: A i.i.d. normal (m x n), (n-2) x k reflectors."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    _, A = _colmajor_buffer(m, n, lda, pad_fill)
+    A[...] = rng.standard_normal(m * n).reshape(n, m).T
+    TAU, NU1, NU2 = make_reflectors3(max(n - 2, 0), k, rng, lds=lds, pad_fill=pad_fill)
+    return Refl3Problem(m, n, k, A, TAU, NU1, NU2)
+
+
 def make_cs(n, k, rng):
     """Fresh rotation coefficients (n-1) x k, contiguous column-major."""
     nm1 = max(n - 1, 0)

@@ -213,3 +213,44 @@ def test_left_workspace_adds_packed_copy():
     assert rs.workspace_bytes("float64", 1, 70, 16, {"left": 1}) == 0
     assert rs.workspace_bytes("float64", 300, 0, 16, {"left": 1}) == 0
     assert rs.workspace_bytes("float64", 300, 1, 16, {"left": 1}) > 0
+
+
+def _r3(fn, m, n, k, A, lda, T, ldt, N1, ld1, N2, ld2, ws=None, wsb=0):
+    lib = ctypes.CDLL(rs.library_path())
+    f = getattr(lib, fn)
+    f.restype = ctypes.c_int
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    f.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, ctypes.c_size_t]
+    return f(m, n, k, A, lda, T, ldt, N1, ld1, N2, ld2, None, ws, wsb)
+
+
+@pytest.mark.parametrize("fn", ["rotseq_refl3_d", "rotseq_refl3_s"])
+def test_refl3_argument_checks_without_device(fn):
+    """Arguments are checked in order (-i for argument i) before anything
+    touches the device; TAU/NU1/NU2 need n-2 rows; quick returns accept NULL."""
+    ok = (6, 10, 3, 1, 6, 1, 8, 1, 8, 1, 8)
+    for pos, bad in [(0, -1), (1, -1), (2, -1), (3, None), (4, 5), (5, None), (6, 7), (7, None),
+                     (8, 7), (9, None), (10, 7)]:
+        args = list(ok)
+        args[pos] = bad
+        assert _r3(fn, *args) == -(pos + 1), (pos, bad)
+    assert _r3(fn, 0, 10, 3, None, 1, None, 8, None, 8, None, 8) == 0
+    assert _r3(fn, 6, 2, 3, None, 6, None, 1, None, 1, None, 1) == 0
+    assert _r3(fn, 6, 10, 0, None, 6, None, 8, None, 8, None, 8) == 0
+    # a caller workspace that is too small or misaligned is refused before any launch
+    assert _r3(fn, *ok, ws=256, wsb=16) == 3
+    assert _r3(fn, *ok, ws=0x1001, wsb=1 << 30) == 3
+
+
+def test_refl3_workspace_bytes():
+    """Records of (tau, nu1, nu2) for bands of 8 sequences over the padded
+    wavefront steps; zero for quick-return shapes and unknown dtypes."""
+    lib = ctypes.CDLL(rs.library_path())
+    f = lib.rotseq_refl3_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_char, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    d = f(b"d", 10240, 10240, 192)
+    assert d >= 192 * 10240 * 3 * 8 and d < 192 * (10240 + 64) * 3 * 8 + 256
+    assert f(b"s", 10240, 10240, 192) * 2 >= d - 256
+    assert f(b"d", 0, 100, 8) == 0 and f(b"d", 5, 2, 8) == 0 and f(b"d", 5, 100, 0) == 0
+    assert f(b"x", 5, 100, 8) == 0

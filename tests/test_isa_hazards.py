@@ -1,6 +1,7 @@
-"""Static check of the chain kernel's gfx950 assembly (CPU only).
+"""Static check of the gfx950 assembly of the chain kernel and of the 3x3
+reflector sweep (CPU only).
 
-The sweep reads coefficients through DPP (row_newbcast) operands written in
+Both sweeps read coefficients through DPP (row_newbcast) operands written in
 inline assembly, where the compiler cannot insert the two wait states the
 hardware needs between a VALU write of a VGPR and a DPP read of it.  The
 kernel is built so that every DPP source is written by a memory load; this
@@ -29,15 +30,15 @@ def vregs(text):
     return out
 
 
-@pytest.fixture(scope="module")
-def chain_asm(tmp_path_factory):
+@pytest.fixture(scope="module", params=["rotseq_chain.hip", "rotseq_refl3.hip"])
+def chain_asm(request, tmp_path_factory):
     if not shutil.which(HIPCC) and not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
-    out = tmp_path_factory.mktemp("isa") / "chain.s"
+    out = tmp_path_factory.mktemp("isa") / (request.param + ".s")
     from paper_2412_01852_amd import build
     # the library's own flags, so the scanned code is the code that runs
     cmd = [HIPCC, *build.FLAGS, "--cuda-device-only", "-S",
-           os.path.join(CSRC, "rotseq_chain.hip"), "-o", str(out)]
+           os.path.join(CSRC, request.param), "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True)
     return out.read_text()
 
@@ -72,6 +73,6 @@ def test_no_scratch_spills(chain_asm):
     for m in re.finditer(r"\.name:\s+(\S*sweep_chain\S*)(.*?)\.vgpr_spill_count:\s+(\d+)", chain_asm, re.S):
         pass
     spills = re.findall(r"\.vgpr_spill_count:\s+(\d+)", chain_asm)
-    assert spills and all(int(v) == 0 for v in spills), "VGPR spills in the chain kernel"
+    assert spills and all(int(v) == 0 for v in spills), "VGPR spills in a sweep kernel"
     assert "private_segment_fixed_size: 0" in chain_asm.replace("  ", " ") or \
         all(int(v) == 0 for v in re.findall(r"\.private_segment_fixed_size:\s+(\d+)", chain_asm))
