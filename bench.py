@@ -62,11 +62,11 @@ def _code_only(text):
     return " ".join(text.split())
 
 
-def kernel_source_hash():
-    """Hash of the code (comments excluded) the sweep kernel is compiled from."""
+def kernel_source_hash(sources=SWEEP_SOURCES):
+    """Hash of the code (comments excluded) a sweep kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2412_01852_amd", "csrc")
-    for f in SWEEP_SOURCES:
+    for f in sources:
         with open(os.path.join(csrc, f)) as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
@@ -81,9 +81,9 @@ def measured_traffic(workload, launch_bytes_alg):
             rec = json.load(f).get(workload)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(rec.get("sources", SWEEP_SOURCES)):
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", rec.get("bytes_per_call"))
 
 
 def cpu_model():
@@ -525,6 +525,10 @@ def main():
             "hbm_bound_ms": round(alg_bytes / (HBM_GBS * 1e9) * 1e3, 4),
         },
     }
+    if variant == "refl3":
+        # one call sweeps its bands in launches of at most 12 waves
+        nb = (k + 7) // 8
+        out["roofline"]["sweep_launches_per_call"] = (nb + 11) // 12
     if variant == "left":
         # prep_ms includes packing A^T into the workspace and unpacking it
         out["roofline"]["packing_bytes"] = 4.0 * esize * m * n
