@@ -32,7 +32,8 @@
 // FMAs through the DPP row_newbcast operand modifier (a copy of x into w
 // makes it six instructions).  Scalar loads would be simpler, but they
 // complete out of order, so a wave can only wait for all of them: every
-// step would wait for its own records.  FP32 uses scalar loads.
+// step would wait for its own records.  FP32 does the same with 32-bit
+// DPP (quad_perm broadcast within each quad of lanes).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -129,6 +130,22 @@ __device__ __forceinline__ void reflect3_dpp(double &x, double &y, double &z, do
 }
 #undef R3_FMAC
 
+// FP32: the same with record fields broadcast from lane S0..S4 of each quad
+// of a0..a4 (DPP quad_perm); 32-bit DPP has no row_newbcast.
+#define R3_FMAC32(X, A, Y, S) \
+    "v_fmac_f32_dpp %" #X ", %" #A ", %" #Y " quad_perm:[%" #S ",%" #S ",%" #S ",%" #S "] row_mask:0xf bank_mask:0xf\n"
+template <int S0, int S1, int S2, int S3, int S4>
+__device__ __forceinline__ void reflect3_dpp32(float &x, float &y, float &z, float a0, float a1,
+                                               float a2, float a3, float a4)
+{
+    float w;
+    asm("v_mov_b32 %3, %0\n" R3_FMAC32(3, 4, 1, 9) R3_FMAC32(3, 5, 2, 10) R3_FMAC32(0, 6, 3, 11)
+            R3_FMAC32(1, 7, 3, 12) R3_FMAC32(2, 8, 3, 13)
+        : "+v"(x), "+v"(y), "+v"(z), "=&v"(w)
+        : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "n"(S0), "n"(S1), "n"(S2), "n"(S3), "n"(S4));
+}
+#undef R3_FMAC32
+
 // Records in wavefront order: for band g (sequences gK .. gK+K-1), local step
 // t and member q, rec[((g * steps + t) * K + q) * 5 + {0..4}] holds
 // (nu1, nu2, -tau, -tau nu1, -tau nu2) of reflector (t - 2q, gK + q), or
@@ -172,8 +189,9 @@ struct Refl3Args {
 // At most 12 waves (bands) per workgroup: 3 waves per SIMD leave each wave
 // up to 168 VGPRs.
 constexpr int kRefl3MaxWaves = 12;
-// Sequences per band (per wave).
-constexpr int kRefl3Band = 8;
+// Sequences per band (per wave): FP32 keeps its records of a group in half
+// the registers with bands of 4.
+constexpr int refl3_band(int esize) { return esize == 8 ? 8 : 4; }
 
 template <typename T, int K>
 __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
@@ -247,21 +265,25 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
         unroll<0, D + 2>([&](auto ic) { x[decltype(ic)::value] = fetch(decltype(ic)::value, role); });
     });
 
-    // Records through DPP (FP64 interior chunks): a group's G*K records
-    // are NB blocks of 32 (16 bytes per lane, lane l of each row holding
-    // records 2l and 2l+1), in register set (group index) mod 2.
-    constexpr bool DPP = sizeof(T) == 8 && (G * K * kRec) % 32 == 0;
-    constexpr int NB = DPP ? G * K * kRec / 32 : 1;
-    typedef double f64x2 __attribute__((ext_vector_type(2)));
-    using GV = __attribute__((address_space(1))) const f64x2;
-    f64x2 rd[2][NB];
-    const uint64_t rec_b = (uint64_t)rec_v + (lane & 15) * 16;
+    // Records through DPP: a group's G*K records are NB blocks of BLK, 16
+    // bytes per lane, in register set (group index) mod 2.  FP64: blocks of
+    // 32, lane l of each 16-lane row holding records 2l and 2l+1 (read with
+    // row_newbcast).  FP32: blocks of 16, lane s of each quad holding records
+    // 4s..4s+3 (read with quad_perm).
+    constexpr int PER = 16 / sizeof(T);              // records per lane and load
+    constexpr int BLK = sizeof(T) == 8 ? 32 : 16;    // records per block
+    constexpr bool DPP = (G * K * kRec) % BLK == 0;
+    constexpr int NB = DPP ? G * K * kRec / BLK : 1;
+    typedef T tx4 __attribute__((ext_vector_type(PER)));
+    using GV = __attribute__((address_space(1))) const tx4;
+    tx4 rd[2][NB];
+    const uint64_t rec_b = (uint64_t)rec_v + (sizeof(T) == 8 ? (lane & 15) : (lane & 3)) * 16;
     auto load_group = [&](auto setc, int step0) {
         constexpr int SET = decltype(setc)::value;
         const uint64_t base = rec_b + (uint64_t)step0 * K * kRec * sizeof(T);
         unroll<0, NB>([&](auto bc) {
             constexpr int b = decltype(bc)::value;
-            rd[SET][b] = *(GV *)(base + b * 256);
+            rd[SET][b] = *(GV *)(base + b * BLK * sizeof(T));
         });
     };
     bool have_first = false;  // records of the chunk's first group are in set 0
@@ -312,12 +334,22 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
                         return;
                 }
                 if constexpr (VIA_DPP) {
+                    // record field f is element e+f: block (e+f)/BLK, lane
+                    // ((e+f) % BLK)/PER of the row or quad, component (e+f) % PER
                     constexpr int set = (u / G) & 1, e = ((u % G) * K + q) * kRec;
-                    reflect3_dpp<(e % 32) / 2, ((e + 1) % 32) / 2, ((e + 2) % 32) / 2, ((e + 3) % 32) / 2,
-                                 ((e + 4) % 32) / 2>(
-                        x[s], x[(s + 1) % R], x[(s + 2) % R], rd[set][e / 32][e & 1],
-                        rd[set][(e + 1) / 32][(e + 1) & 1], rd[set][(e + 2) / 32][(e + 2) & 1],
-                        rd[set][(e + 3) / 32][(e + 3) & 1], rd[set][(e + 4) / 32][(e + 4) & 1]);
+                    constexpr int L0 = (e % BLK) / PER, L1 = ((e + 1) % BLK) / PER,
+                                  L2 = ((e + 2) % BLK) / PER, L3 = ((e + 3) % BLK) / PER,
+                                  L4 = ((e + 4) % BLK) / PER;
+                    const T a0 = rd[set][e / BLK][e % PER], a1 = rd[set][(e + 1) / BLK][(e + 1) % PER],
+                            a2 = rd[set][(e + 2) / BLK][(e + 2) % PER],
+                            a3 = rd[set][(e + 3) / BLK][(e + 3) % PER],
+                            a4 = rd[set][(e + 4) / BLK][(e + 4) % PER];
+                    if constexpr (sizeof(T) == 8)
+                        reflect3_dpp<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1, a2,
+                                                         a3, a4);
+                    else
+                        reflect3_dpp32<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1,
+                                                           a2, a3, a4);
                 } else {
                     reflect3(x[s], x[(s + 1) % R], x[(s + 2) % R], r0 + (u * K + q) * kRec);
                 }
@@ -392,8 +424,8 @@ bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int 
     p.k = k;
     p.lda = lda;
     p.esize = esize;
-    p.band = kRefl3Band;
-    const int R = p.band == 8 ? R3Geom<8>::R : R3Geom<4>::R;
+    p.band = refl3_band(esize);
+    const int R = esize == 8 ? R3Geom<refl3_band(8)>::R : R3Geom<refl3_band(4)>::R;
     p.nbands = (int)((k + p.band - 1) / p.band);
     // Local steps per band: column n-1 leaves after step n+2K-3.
     const int64_t steps = n + 2 * p.band - 2;
@@ -425,12 +457,10 @@ hipError_t launch_refl3_prep(const Refl3Plan &p, const void *TAU, int64_t ldt, c
 
 hipError_t launch_refl3_sweep(const Refl3Plan &p, void *A, const void *ws, hipStream_t st)
 {
-    if (p.band == 8)
-        return p.esize == 8 ? sweep_launches<double, 8>(p, (double *)A, (const double *)ws, st)
-                            : sweep_launches<float, 8>(p, (float *)A, (const float *)ws, st);
-    if (p.band == 4)
-        return p.esize == 8 ? sweep_launches<double, 4>(p, (double *)A, (const double *)ws, st)
-                            : sweep_launches<float, 4>(p, (float *)A, (const float *)ws, st);
+    if (p.esize == 8 && p.band == refl3_band(8))
+        return sweep_launches<double, refl3_band(8)>(p, (double *)A, (const double *)ws, st);
+    if (p.esize == 4 && p.band == refl3_band(4))
+        return sweep_launches<float, refl3_band(4)>(p, (float *)A, (const float *)ws, st);
     return hipErrorInvalidValue;
 }
 

@@ -243,15 +243,16 @@ def test_refl3_argument_checks_without_device(fn):
 
 
 def test_refl3_workspace_bytes():
-    """Records of (nu1, nu2, -tau, -tau nu1, -tau nu2) for bands of 8
-    sequences over the padded wavefront steps; zero for quick-return shapes
-    and unknown dtypes."""
+    """Records of (nu1, nu2, -tau, -tau nu1, -tau nu2) for bands of 8 (FP64)
+    or 4 (FP32) sequences over the padded wavefront steps; zero for
+    quick-return shapes and unknown dtypes."""
     lib = ctypes.CDLL(rs.library_path())
     f = lib.rotseq_refl3_workspace_bytes
     f.restype = ctypes.c_size_t
     f.argtypes = [ctypes.c_char, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
     d = f(b"d", 10240, 10240, 192)
     assert d >= 192 * 10240 * 5 * 8 and d < 192 * (10240 + 64) * 5 * 8 + 256
-    assert f(b"s", 10240, 10240, 192) * 2 >= d - 256
+    f32 = f(b"s", 10240, 10240, 192)
+    assert f32 >= 192 * 10240 * 5 * 4 and f32 < 192 * (10240 + 64) * 5 * 4 + 256
     assert f(b"d", 0, 100, 8) == 0 and f(b"d", 5, 2, 8) == 0 and f(b"d", 5, 100, 0) == 0
     assert f(b"x", 5, 100, 8) == 0

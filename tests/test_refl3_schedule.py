@@ -125,36 +125,38 @@ def simulate(m, n, k, K, W, A=None, coef=None, check=True):
     return barriers
 
 
-@pytest.mark.parametrize("K", [8])
+@pytest.mark.parametrize("K", [4, 8])
 def test_geometry_conditions(K):
     g = geometry(K)
     G, D, R, L, RB = g["G"], g["D"], g["R"], g["L"], g["RB"]
     assert R >= 2 * K + 1 + D and R % G == 0
     assert L >= 2 * K + D + G and L % G == 0
     assert RB >= 2 * G - 1 and RB >= L + G - 2 * K + 2
-    assert (16 - 1) * RB * 64 * 8 <= 160 * 1024, "FP64 rings of 16 waves must fit the LDS"
+    assert (12 - 1) * RB * 64 * 8 <= 160 * 1024, "FP64 rings of 12 waves must fit the LDS"
 
 
-@pytest.mark.parametrize("n,k,W", [(3, 8, 1), (5, 16, 2), (40, 24, 3), (97, 40, 5), (131, 93, 12), (300, 128, 16)])
-def test_lockstep_events(n, k, W):
+@pytest.mark.parametrize("K", [4, 8])
+@pytest.mark.parametrize("n,k,W", [(3, 8, 1), (5, 16, 2), (40, 24, 3), (97, 40, 5), (131, 93, 12), (300, 96, 12)])
+def test_lockstep_events(n, k, W, K):
     """No ring slot is read before its column was written, after it was
     overwritten, or in the group of a write; barrier counts are equal."""
-    barriers = simulate(1, n, k, 8, W)
+    k = min(k, W * K)
+    barriers = simulate(1, n, k, K, W)
     assert len(set(barriers)) == 1, barriers
 
 
+@pytest.mark.parametrize("K", [4, 8])
 @pytest.mark.parametrize("m,n,k", [(3, 3, 1), (5, 4, 9), (7, 23, 17), (2, 61, 40), (4, 150, 96)])
-def test_schedule_matches_oracle(m, n, k):
-    """The schedule (all launches of at most 16 waves) carries the arithmetic
+def test_schedule_matches_oracle(m, n, k, K):
+    """The schedule (all launches of at most 12 waves) carries the arithmetic
     to the oracle's result within rounding."""
     rng = np.random.Generator(np.random.PCG64(1000 + n))
     nu1, nu2 = rng.standard_normal((n - 2, k)), rng.standard_normal((n - 2, k))
     tau = 2.0 / (1.0 + nu1 ** 2 + nu2 ** 2)
     A0 = rng.standard_normal((m, n))
     A = A0.copy()
-    K = 8
     nb = (k + K - 1) // K
-    launches = (nb + 15) // 16
+    launches = (nb + 11) // 12
     waves = (nb + launches - 1) // launches
     for b0 in range(0, nb, waves):
         W = min(waves, nb - b0)
