@@ -26,14 +26,14 @@
 // the records (nu1, nu2, -tau, -tau nu1, -tau nu2) of the K reflectors of one
 // step side by side.  With the products formed once, a reflector is
 //     w = x + nu1 y + nu2 z;  x += (-tau) w;  y += (-tau nu1) w;  z += (-tau nu2) w,
-// five FMAs per row.  FP64 interior chunks take the records of a group of
-// steps with vector loads, one group ahead, lane l of every 16-lane row
-// holding records 2l and 2l+1 of a 32-record block, and read them in the
-// FMAs through the DPP row_newbcast operand modifier (a copy of x into w
-// makes it six instructions).  Scalar loads would be simpler, but they
-// complete out of order, so a wave can only wait for all of them: every
-// step would wait for its own records.  FP32 does the same with 32-bit
-// DPP (quad_perm broadcast within each quad of lanes).
+// five FMAs per row.  A wave takes the records of a group of steps with
+// vector loads, one group ahead, lane l of every 16-lane row holding records
+// 2l and 2l+1 of a 32-record block, and reads them in the FMAs through the
+// DPP row_newbcast operand modifier (a copy of x into w makes it six
+// instructions).  Scalar loads would be simpler, but they complete out of
+// order, so a wave can only wait for all of them: every step would wait for
+// its own records.  FP32 does the same with 32-bit DPP (quad_perm broadcast
+// within each quad of lanes).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -101,21 +101,12 @@ __device__ __forceinline__ void r3_barrier()
 // Record fields of one reflector.
 constexpr int kRec = 5;  // nu1, nu2, -tau, -tau*nu1, -tau*nu2
 
-// One 3x3 reflector on the entries (x, y, z) of a row, record r.
-template <typename T, typename P>
-__device__ __forceinline__ void reflect3(T &x, T &y, T &z, P r)
-{
-    const T w = fmad(r[1], z, fmad(r[0], y, x));
-    x = fmad(r[2], w, x);
-    y = fmad(r[3], w, y);
-    z = fmad(r[4], w, z);
-}
-
-// The same with the record fields broadcast from lanes L0..L4 of each
-// 16-lane row of a0..a4 (DPP row_newbcast).  A DPP source must not have been
-// written by a VALU instruction in the two preceding instructions, which the
-// compiler cannot see inside the asm; a0..a4 are written by the record loads
-// only (tests scan the ISA).
+// One 3x3 reflector on the entries (x, y, z) of a row, with the record
+// fields broadcast from lanes L0..L4 of each 16-lane row of a0..a4 (DPP
+// row_newbcast): w = x + nu1 y + nu2 z, then x, y, z += (field) * w.  A DPP
+// source must not have been written by a VALU instruction in the two
+// preceding instructions, which the compiler cannot see inside the asm;
+// a0..a4 are written by the record loads only (tests scan the ISA).
 #define R3_FMAC(X, A, Y, L) \
     "v_fmac_f64_dpp %" #X ", %" #A ", %" #Y " row_newbcast:%" #L " row_mask:0xf bank_mask:0xf\n"
 template <int L0, int L1, int L2, int L3, int L4>
@@ -183,7 +174,6 @@ struct Refl3Args {
     int64_t band_stride;   // elements between the records of neighbouring bands
     int m, n;
     int chunks;            // R-step chunks per band
-    int kq_last;           // sequences in the last wave's band (1..K)
 };
 
 // At most 12 waves (bands) per workgroup: 3 waves per SIMD leave each wave
@@ -210,7 +200,6 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
     // values, same work) and store nothing.
     const int lrow = lane < rows ? lane : rows - 1;
     const bool from_a = w == 0, to_a = w == W - 1;
-    const int kq = to_a ? a.kq_last : K;
     const int n = a.n;
     const int64_t lda = a.lda;
     // A through the global address space: flat accesses would also count
@@ -221,7 +210,6 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
     const T *in_ring = ring + (w > 0 ? w - 1 : 0) * RB * kWave + lane;
     T *out_ring = ring + w * RB * kWave + lane;
     const T *rec_v = reinterpret_cast<const T *>(a.rec) + w * a.band_stride;
-    ConstScalars<T> rec = (ConstScalars<T>)rec_v;
 
     // Column sources and sinks.  ROLE bit 0: this wave reads A (else the
     // previous wave's ring); bit 1: it writes A (else its own ring).  Lanes
@@ -272,8 +260,8 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
     // 4s..4s+3 (read with quad_perm).
     constexpr int PER = 16 / sizeof(T);              // records per lane and load
     constexpr int BLK = sizeof(T) == 8 ? 32 : 16;    // records per block
-    constexpr bool DPP = (G * K * kRec) % BLK == 0;
-    constexpr int NB = DPP ? G * K * kRec / BLK : 1;
+    static_assert((G * K * kRec) % BLK == 0, "a group's records fill whole blocks");
+    constexpr int NB = G * K * kRec / BLK;
     typedef T tx4 __attribute__((ext_vector_type(PER)));
     using GV = __attribute__((address_space(1))) const tx4;
     tx4 rd[2][NB];
@@ -289,26 +277,25 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
     bool have_first = false;  // records of the chunk's first group are in set 0
     const int steps = a.chunks * R;
 
-    // One chunk of R steps.  Edge chunks (GUARD) test every reflector for
-    // existence; interior chunks are straight-line code between barriers.
+    // One chunk of R steps.  Edge chunks (GUARD) check the columns they
+    // fetch and store against A; interior chunks are straight-line code
+    // between barriers.  Reflectors that do not exist (before column 0, past
+    // column n-3, past sequence k-1) have zero records: an exact identity on
+    // finite entries.
     const uint64_t ldab = (uint64_t)lda * sizeof(T);
     auto chunk = [&](int t0, auto guarded, auto role) {
         constexpr bool GUARD = decltype(guarded)::value;
-        constexpr bool VIA_DPP = DPP;
-        ConstScalars<T> r0 = rec + (int64_t)t0 * K * kRec;
         // Running column addresses (fetch: column t+2+D; store: column
         // t-2K+2), kept opaque so that the unrolled steps share one SGPR pair
         // each instead of one 64-bit offset per step.
         uint64_t fa = (uint64_t)(A + (int64_t)(t0 + 2 + D) * lda);
         uint64_t sa = (uint64_t)(A + (int64_t)(t0 - 2 * K + 2) * lda);
-        if constexpr (VIA_DPP) {
-            if (!have_first)
-                load_group(std::integral_constant<int, 0>{}, t0);
-        }
+        if (!have_first)
+            load_group(std::integral_constant<int, 0>{}, t0);
         unroll<0, R>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
             const int t = t0 + u;
-            if constexpr (VIA_DPP && u % G == 0) {
+            if constexpr (u % G == 0) {
                 // records of the next group (after the last group, the next
                 // chunk's first; interior chunks are never the last chunk)
                 if (!GUARD || u + G < R || t + G < steps)
@@ -326,33 +313,22 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
             unroll<0, K>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 constexpr int s = (u - 2 * q + 2 * R) % R;  // slot of column t - 2q
-                // Reflectors that do not exist have zero records, an exact
-                // identity on finite entries; the scalar path skips them.
-                if constexpr (GUARD && !VIA_DPP) {
-                    const int j = t - 2 * q;
-                    if (q >= kq || j < 0 || j >= n - 2)
-                        return;
-                }
-                if constexpr (VIA_DPP) {
-                    // record field f is element e+f: block (e+f)/BLK, lane
-                    // ((e+f) % BLK)/PER of the row or quad, component (e+f) % PER
-                    constexpr int set = (u / G) & 1, e = ((u % G) * K + q) * kRec;
-                    constexpr int L0 = (e % BLK) / PER, L1 = ((e + 1) % BLK) / PER,
-                                  L2 = ((e + 2) % BLK) / PER, L3 = ((e + 3) % BLK) / PER,
-                                  L4 = ((e + 4) % BLK) / PER;
-                    const T a0 = rd[set][e / BLK][e % PER], a1 = rd[set][(e + 1) / BLK][(e + 1) % PER],
-                            a2 = rd[set][(e + 2) / BLK][(e + 2) % PER],
-                            a3 = rd[set][(e + 3) / BLK][(e + 3) % PER],
-                            a4 = rd[set][(e + 4) / BLK][(e + 4) % PER];
-                    if constexpr (sizeof(T) == 8)
-                        reflect3_dpp<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1, a2,
-                                                         a3, a4);
-                    else
-                        reflect3_dpp32<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1,
-                                                           a2, a3, a4);
-                } else {
-                    reflect3(x[s], x[(s + 1) % R], x[(s + 2) % R], r0 + (u * K + q) * kRec);
-                }
+                // record field f is element e+f: block (e+f)/BLK, lane
+                // ((e+f) % BLK)/PER of the row or quad, component (e+f) % PER
+                constexpr int set = (u / G) & 1, e = ((u % G) * K + q) * kRec;
+                constexpr int L0 = (e % BLK) / PER, L1 = ((e + 1) % BLK) / PER,
+                              L2 = ((e + 2) % BLK) / PER, L3 = ((e + 3) % BLK) / PER,
+                              L4 = ((e + 4) % BLK) / PER;
+                const T a0 = rd[set][e / BLK][e % PER], a1 = rd[set][(e + 1) / BLK][(e + 1) % PER],
+                        a2 = rd[set][(e + 2) / BLK][(e + 2) % PER],
+                        a3 = rd[set][(e + 3) / BLK][(e + 3) % PER],
+                        a4 = rd[set][(e + 4) / BLK][(e + 4) % PER];
+                if constexpr (sizeof(T) == 8)
+                    reflect3_dpp<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1, a2, a3,
+                                                     a4);
+                else
+                    reflect3_dpp32<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1, a2,
+                                                       a3, a4);
             });
             const int c = t - 2 * K + 2;
             const T v = x[(u - 2 * K + 2 + 2 * R) % R];
@@ -368,14 +344,13 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
             if constexpr ((u + 1) % G == 0)
                 r3_barrier();
         });
-        have_first = VIA_DPP && t0 + R < steps;
+        have_first = t0 + R < steps;
     };
 
     for (int ch = 0; ch < a.chunks; ++ch) {
         const int t0 = ch * R;
-        // Interior chunks: every reflector of the band exists and every
-        // column fetched or stored is inside A.
-        const bool interior = kq == K && t0 >= 2 * K - 2 && t0 + R + D + 1 < n;
+        // Interior chunks: every column fetched or stored is inside A.
+        const bool interior = t0 >= 2 * K - 2 && t0 + R + D + 1 < n;
         if (interior)
             with_role([&](auto role) { chunk(t0, std::false_type{}, role); });
         else
@@ -402,8 +377,6 @@ hipError_t sweep_launches(const Refl3Plan &p, T *A, const T *rec, hipStream_t st
         a.m = (int)p.m;
         a.n = (int)p.n;
         a.chunks = p.steps / Gm::R;
-        const int64_t last = (int64_t)(b0 + W - 1) * K;
-        a.kq_last = (int)(p.k - last < K ? p.k - last : K);
         const size_t lds = W > 1 ? (size_t)(W - 1) * Gm::RB * kWave * sizeof(T) : 4;
         refl3_sweep<T, K><<<tiles, W * kWave, lds, st>>>(a);
         const hipError_t e = hipGetLastError();
