@@ -111,18 +111,20 @@ def test_refl3_caller_workspace():
         rs.refl3seq(A, *(to_dev(X, "f64") for X in (pb.TAU, pb.NU1, pb.NU2)), workspace=small)
 
 
-def test_refl3_full_size_sampled_rows():
-    """10240 x 10240, k = 192 (FP64): rows are independent, so the oracle
-    computes a sample of rows (first, last, and across tiles) exactly."""
-    say("refl3 full size 10240x10240 k=192 f64")
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_refl3_full_size_sampled_rows(dtype):
+    """10240 x 10240, k = 192 in the bench's launch configuration: rows are
+    independent, so the oracle computes a sample of rows (first, last, and
+    across tiles) exactly."""
+    say(f"refl3 full size 10240x10240 k=192 {dtype}")
     m = n = 10240
     k = 192
     pb = make_refl3_problem(m, n, k, seed=3)
-    A = _run(pb, "f64")
+    A = _run(pb, dtype)
     rows = np.array([0, 1, 63, 64, 4097, 7777, m - 65, m - 1])
-    got = A[torch_index(rows)].detach().cpu().numpy()
-    ref = _oracle(pb, "f64", rows)
-    assert relerr(got, ref, np.asarray(pb.A)[rows]) <= TOL["f64"]
+    got = A[torch_index(rows)].detach().cpu().to(dtype=__import__("torch").float64).numpy()
+    ref = _oracle(pb, dtype, rows)
+    assert relerr(got, ref, widened(pb.A, dtype)[rows]) <= TOL[dtype]
 
 
 def torch_index(rows):
