@@ -98,15 +98,23 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(pb, dtype, target_s=15.0):
-    """The oracle (threaded over rows) on a bounded sample of rows."""
-    import numpy as np
-    import oracle
+def host_threads():
+    """Host threads of this process (its CPU affinity), at most 16: the CPU
+    share of one GPU on an MI355X host, where worker pools are sized to it."""
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         threads = os.cpu_count() or 1
-    threads = max(1, min(threads, 16))
+    return max(1, min(threads, 16))
+
+
+def cpu_baseline(pb, dtype, target_s=15.0):
+    """The oracle on a bounded sample of rows: threaded over rows on the
+    host threads (the reported value), and on one thread (Algorithm 2 as a
+    plain loop, the paper's unoptimized shape)."""
+    import numpy as np
+    import oracle
+    threads = host_threads()
     m, n, k = pb.m, pb.n, pb.k
     A = np.asarray(pb.A)
     if dtype == "f32":
@@ -114,25 +122,33 @@ def cpu_baseline(pb, dtype, target_s=15.0):
     Cw = np.asfortranarray(np.asarray(pb.C, dtype=np.float32 if dtype == "f32" else np.float64), dtype=np.float64)
     Sw = np.asfortranarray(np.asarray(pb.S, dtype=np.float32 if dtype == "f32" else np.float64), dtype=np.float64)
 
-    def timed(rows):
+    def timed(rows, thr):
         sub = oracle.colmajor(A[:rows])
         t0 = time.perf_counter()
-        oracle.rotseq(sub, Cw, Sw, threads=threads)
+        oracle.rotseq(sub, Cw, Sw, threads=thr)
         return time.perf_counter() - t0
 
-    # Grow the sample until it takes at least half the target time (small
-    # samples are dominated by thread start-up, so one extrapolation from
-    # them undershoots), then time it.
-    rows = min(m, 4 * threads)
-    dt = timed(rows)
-    while dt < 0.5 * target_s and rows < m:
-        rows = int(min(m, max(2 * rows, rows * target_s / max(dt, 1e-3))))
-        rows = max(threads, (rows // threads) * threads) if rows >= threads else rows
-        dt = timed(rows)
+    def sample(thr, target):
+        # Grow the sample until it takes at least half the target time
+        # (small samples are dominated by thread start-up, so one
+        # extrapolation from them undershoots), then time it.
+        rows = min(m, 4 * thr)
+        dt = timed(rows, thr)
+        while dt < 0.5 * target and rows < m:
+            rows = int(min(m, max(2 * rows, rows * target / max(dt, 1e-3))))
+            rows = max(thr, (rows // thr) * thr) if rows >= thr else rows
+            dt = timed(rows, thr)
+        return rows, dt
+
+    rows, dt = sample(threads, 0.6 * target_s)
+    rows1, dt1 = sample(1, 0.4 * target_s)
     gf = 6.0 * rows * (n - 1) * k / dt / 1e9
+    gf1 = 6.0 * rows1 * (n - 1) * k / dt1 / 1e9
     return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} of {m} rows x all {n} columns x all {k} sequences "
-                      f"({dt:.1f} s, FP64 oracle, row-partitioned threads)",
+                      f"({dt:.1f} s, FP64 oracle, rows split over {threads} threads)",
+            "single_thread": {"value": round(gf1, 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"{rows1} of {m} rows ({dt1:.1f} s, one thread)"},
             "cpu": cpu_model()}
 
 
@@ -212,7 +228,7 @@ def bench_batched(args):
     e1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+    assert batch.status()[0] == 0, "a device-side wait of the batch timed out"
     ms_step = (t1 - t0) * 1e3 / args.steps
     ms_dev = e0.elapsed_time(e1) / args.steps
     # The same problems as a loop of single calls on one stream (context).
@@ -393,6 +409,35 @@ def bench_served(args):
     return 0
 
 
+def trace_summary(path, last):
+    """Per-kernel durations from rocprofv3 kernel-trace CSV files under
+    `path`, over each kernel's last `last` dispatches (0: all), as a
+    markdown table: the steady-state figures of a bench run whose warm-up
+    calls come first."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True))
+    if not files:
+        print(f"no kernel_trace.csv under {path}", file=sys.stderr)
+        return 1
+    runs = {}
+    for fn in files:
+        with open(fn, newline="") as f:
+            for row in csv.DictReader(f):
+                t0, t1 = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+                runs.setdefault(row["Kernel_Name"], []).append((t0, t1 - t0))
+    total = sum(d for v in runs.values() for _, d in v)
+    print(f"| Kernel | Calls | Steady calls | Average (us) | Min (us) | Max (us) | Share of all |")
+    print("|---|---|---|---|---|---|---|")
+    for name, v in sorted(runs.items(), key=lambda kv: -sum(d for _, d in kv[1])):
+        v.sort()
+        tail = [d for _, d in (v[-last:] if last else v)]
+        print(f"| `{name}` | {len(v)} | {len(tail)} | {sum(tail) / len(tail) / 1e3:.1f} | "
+              f"{min(tail) / 1e3:.1f} | {max(tail) / 1e3:.1f} | "
+              f"{100.0 * sum(d for _, d in v) / total:.2f}% |")
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,7 +456,13 @@ def main():
                     help="served workload: draw k for every sweep instead of once per request")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="only summarise the rocprofv3 kernel traces under DIR (no GPU)")
+    ap.add_argument("--last", type=int, default=0,
+                    help="--trace-summary: per kernel, only its last N dispatches")
     args = ap.parse_args()
+    if args.trace_summary:
+        return trace_summary(args.trace_summary, args.last)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(rows shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
@@ -486,9 +537,18 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     gflops = flops / (ms_step * 1e-3) / 1e9
     sweep_ms = prof["sweep_ms"] / max(prof["calls"], 1)
-    achieved = flops / (sweep_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[dtype]
     traffic = measured_traffic(args.workload, alg_bytes)
+    # Roofline of the sweep: the larger of its compute time at the vector
+    # peak and its compulsory HBM time (A read and written once, the
+    # coefficients read once) decides the bound.
+    t_alu = flops / (PEAK_TFLOPS[dtype] * 1e12) * 1e3
+    t_hbm = alg_bytes / (HBM_GBS * 1e9) * 1e3
+    if t_hbm > t_alu:
+        bound, unit, peak = "hbm", "GB/s", HBM_GBS
+        achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    else:
+        bound, unit, peak = "alu", "TFLOP/s", PEAK_TFLOPS[dtype]
+        achieved = flops / (sweep_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": round(gflops, 2),
@@ -511,23 +571,28 @@ def main():
                    "sequences_mix": "rows" if variant == "left" else "columns",
                    "elements": {"refl": "reflectors", "refl3": "3x3 reflectors"}.get(variant, "rotations")},
         "roofline": {
-            "bound": "alu",
+            "bound": bound,
             "achieved": round(achieved, 3),
             "peak": peak,
-            "unit": "TFLOP/s",
+            "unit": unit,
             "frac": round(achieved / peak, 4),
             "traffic": traffic,
             "kernel": "sweep",
             "kernel_ms": round(sweep_ms, 4),
             "kernel_ms_min": round(prof["sweep_ms_min"], 4),
             "prep_ms": round(prof["prep_ms"] / max(prof["calls"], 1), 4),
+            "algorithmic_flops": flops,
             "algorithmic_bytes": alg_bytes,
-            "hbm_bound_ms": round(alg_bytes / (HBM_GBS * 1e9) * 1e3, 4),
+            "alu_bound_ms": round(t_alu, 4),
+            "hbm_bound_ms": round(t_hbm, 4),
+            "tflops_achieved": round(flops / (sweep_ms * 1e-3) / 1e12, 3),
+            "hbm_gbs_achieved": round(alg_bytes / (sweep_ms * 1e-3) / 1e9, 1),
         },
     }
     if variant == "refl3":
-        # one call sweeps its bands in launches of at most 12 waves
-        nb = (k + 7) // 8
+        # one call sweeps its bands (8 sequences in FP64, 4 in FP32) in
+        # launches of at most 12 bands
+        nb = (k + (7 if dtype == "f64" else 3)) // (8 if dtype == "f64" else 4)
         out["roofline"]["sweep_launches_per_call"] = (nb + 11) // 12
     if variant == "left":
         # prep_ms includes packing A^T into the workspace and unpacking it

@@ -53,6 +53,12 @@ extern "C" {
 #define ROTSEQ_E_CLOSED       8  /* the matrix was closed                       */
 #define ROTSEQ_E_FAILED       9  /* an earlier sweep of this matrix failed      */
 
+/* Bit of the device status word (rotseq_device_status) set by the
+ * preparation kernels of rotseq_refl_ex_{d,s} when a reflector with tau != 0
+ * is not orthogonal (|tau (1 + nu^2) - 2| > 64 eps of the element type):
+ * the result of that call is then not A H. */
+#define ROTSEQ_STATUS_NOT_ORTHOGONAL (1 << 16)
+
 /* Arithmetic used for one rotation (options.arith). */
 #define ROTSEQ_ARITH_AUTO   0  /* library choice (currently ROTSEQ_ARITH_LIFT) */
 /* Algorithm 1 exactly: two rounded products and one rounded sum per output,
@@ -181,7 +187,11 @@ int rotseq_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
  * tau * (1 + nu^2) = 2 up to rounding, as LAPACK's dlarfg produces.  The
  * library applies each one as a rotation followed by negating one column
  * (the negations are tracked and undone as in ROTSEQ_ARITH_LIFT), so
- * other values give results that are not A H.  This is not checked.
+ * other values give results that are not A H.  The preparation kernels
+ * check every reflector on the device and set ROTSEQ_STATUS_NOT_ORTHOGONAL
+ * in the device status word (rotseq_device_status) when one is not
+ * orthogonal to within 64 eps; the call itself returns before that check
+ * runs.
  * Only ROTSEQ_ARITH_AUTO / ROTSEQ_ARITH_LIFT are supported
  * (ROTSEQ_E_UNSUPPORTED otherwise).  Workspace as for rotseq_ex_d.
  */
@@ -263,12 +273,30 @@ int rotseq_profile_enable(int on);
 int rotseq_profile_read(rotseq_profile *out, int reset);
 
 /*
- * Sticky device-side error word of the current device.  Kernels OR
- * ROTSEQ_E_* bits into it (ROTSEQ_E_TIMEOUT: a bounded wait between waves
- * gave up, so the affected results are invalid).  This call synchronizes the
- * device, returns the word and, if `reset` is nonzero, clears it.
+ * Sticky device-side error word of the current device, written by the
+ * kernels of the plain calls (rotseq_d/_s, rotseq_ex_*, rotseq_refl_ex_*):
+ * its low byte is ROTSEQ_E_TIMEOUT once a bounded wait between workgroups
+ * has given up (the results of that call are then invalid; bits 8-15 say
+ * which kind of wait), and ROTSEQ_STATUS_NOT_ORTHOGONAL is set when a
+ * reflector call was given a reflector that is not orthogonal.  Batch
+ * plans and the server keep their own words (rotseq_batch_status, ticket
+ * statuses).  This call synchronizes the device, returns the word and, if
+ * `reset` is nonzero, clears it.
  */
 int rotseq_device_status(int reset);
+
+/*
+ * Test hook for the error paths of the bounded waits.  Every chain sweep
+ * launched after this call (plain calls, batch executions, server batches)
+ * gives up a wait between workgroups after `spin_limit` polls (0 restores
+ * the default, 2^22; -1 for a negative value), and with `unreachable`
+ * nonzero every such wait asks for a column count no producer reaches, so
+ * each one gives up: the kernels still run to completion, their results
+ * are wrong, and the failure surfaces as documented for each call
+ * (rotseq_device_status, rotseq_batch_status and rotseq_batched_*'s
+ * return value, ticket statuses).  Process-wide; not for production use.
+ */
+int rotseq_test_set_waits(int32_t spin_limit, int32_t unreachable);
 
 /*
  * Batches (many independent problems in one launch sequence).
@@ -310,8 +338,9 @@ typedef struct rotseq_problem_s {
 /*
  * rotseq_batched_d / rotseq_batched_s: one-shot batch.  Builds a batch plan,
  * runs it on `stream`, waits for the stream and frees the plan, so it blocks
- * until the batch is done.  For repeated batches or HIP graph capture use
- * the plan calls below.
+ * until the batch is done.  Returns ROTSEQ_E_TIMEOUT if a bounded wait of
+ * the sweep gave up (the results are then invalid).  For repeated batches
+ * or HIP graph capture use the plan calls below.
  */
 int rotseq_batched_d(int32_t count, const rotseq_problem_d *probs, hipStream_t stream);
 int rotseq_batched_s(int32_t count, const rotseq_problem_s *probs, hipStream_t stream);
@@ -375,6 +404,17 @@ int rotseq_batch_execute(rotseq_batch *batch, hipStream_t stream);
 int rotseq_batch_update_d(rotseq_batch *batch, int32_t count, const rotseq_problem_d *probs);
 int rotseq_batch_update_s(rotseq_batch *batch, int32_t count, const rotseq_problem_s *probs);
 int rotseq_batch_tune(rotseq_batch *batch, hipStream_t stream, int32_t reps);
+/*
+ * rotseq_batch_status: error words of a plan's entries.  Every entry keeps
+ * a sticky word (zero at creation) into which its sweep records
+ * ROTSEQ_E_TIMEOUT when a bounded wait between workgroups gives up, which
+ * leaves that entry's A invalid.  Synchronizes the device, then writes each
+ * entry's ROTSEQ_E_* code (0 if none) to per_problem[i] for the entries in
+ * creation order (per_problem may be NULL; else it holds `count` entries)
+ * and, if `reset` is nonzero, clears the words.  Returns 0, ROTSEQ_E_TIMEOUT
+ * if any entry failed, -1 for a NULL plan or ROTSEQ_E_HIP.
+ */
+int rotseq_batch_status(rotseq_batch *batch, int32_t *per_problem, int reset);
 int rotseq_batch_info_get(const rotseq_batch *batch, rotseq_batch_info *info);
 int rotseq_batch_destroy(rotseq_batch *batch);
 
@@ -408,7 +448,11 @@ typedef struct rotseq_server_config {
 } rotseq_server_config;
 
 typedef struct rotseq_sweep_info {
-    int32_t status;            /* 0, or the ROTSEQ_E_* code of the failure   */
+    int32_t status;            /* 0, or the ROTSEQ_E_* code of the failure
+                                  (ROTSEQ_E_TIMEOUT: a bounded wait of the
+                                  sweep kernel gave up, so A is invalid;
+                                  the matrix's later sweeps then fail with
+                                  ROTSEQ_E_FAILED)                          */
     int32_t reserved;
     double submit_us;          /* host clock, microseconds since create      */
     double start_us;           /* its batch was launched                     */

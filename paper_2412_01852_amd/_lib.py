@@ -91,6 +91,18 @@ def device_status(reset=False):
     return _load().rotseq_device_status(1 if reset else 0)
 
 
+STATUS_NOT_ORTHOGONAL = 1 << 16
+
+
+def test_set_waits(spin_limit=0, unreachable=False):
+    """rotseq_test_set_waits: bounded waits between workgroups give up after
+    ``spin_limit`` polls (0 = default); with ``unreachable`` every such wait
+    gives up (a test hook for the error paths)."""
+    rc = _load().rotseq_test_set_waits(int(spin_limit), 1 if unreachable else 0)
+    if rc != 0:
+        raise RotseqError(rc, "test_set_waits")
+
+
 def library_path():
     return LIB_PATH
 
@@ -127,6 +139,8 @@ def _load():
     lib.rotseq_version.argtypes = []
     lib.rotseq_device_status.restype = i32
     lib.rotseq_device_status.argtypes = [i32]
+    lib.rotseq_test_set_waits.restype = i32
+    lib.rotseq_test_set_waits.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.rotseq_profile_enable.restype = i32
     lib.rotseq_profile_enable.argtypes = [i32]
     lib.rotseq_profile_read.restype = i32
@@ -144,6 +158,8 @@ def _load():
         f = getattr(lib, name)
         f.restype, f.argtypes = i32, [vp, ctypes.c_int32, pp]
     lib.rotseq_batch_tune.restype, lib.rotseq_batch_tune.argtypes = i32, [vp, vp, ctypes.c_int32]
+    lib.rotseq_batch_status.restype = i32
+    lib.rotseq_batch_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32]
     lib.rotseq_batch_info_get.restype = i32
     lib.rotseq_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     lib.rotseq_batch_destroy.restype, lib.rotseq_batch_destroy.argtypes = i32, [vp]
@@ -403,6 +419,15 @@ class Batch:
         rc = _load().rotseq_batch_tune(self._handle, _stream(stream), int(reps))
         if rc != 0:
             raise RotseqError(rc, "batch_tune")
+
+    def status(self, reset=False):
+        """(return code, per-entry ROTSEQ_E_* codes in creation order) of
+        rotseq_batch_status; synchronizes the device."""
+        words = (ctypes.c_int32 * max(len(self._keep), 1))()
+        rc = _load().rotseq_batch_status(self._handle, words, 1 if reset else 0)
+        if rc not in (0, 5):
+            raise RotseqError(rc, "batch_status")
+        return rc, [int(words[i]) for i in range(len(self._keep))]
 
     def info(self):
         out = BatchInfo()

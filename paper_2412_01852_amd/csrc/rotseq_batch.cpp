@@ -22,7 +22,8 @@ size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
     constexpr int kUnroll = 16;  // step unroll of the chain kernel
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     items.clear();
-    size_t off = a256((size_t)count * sizeof(BatchItem));
+    L.status_off = (size_t)count * sizeof(BatchItem);
+    size_t off = a256(L.status_off + (size_t)count * sizeof(int));
     int64_t o_neg = 0, o_par = 0, o_sign = 0, o_coef = 0, o_flags = 0;
     for (int i = 0; i < count; ++i) {
         const BatchEntry &e = entries[i];
@@ -51,6 +52,7 @@ size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
         off = a256(off + (size_t)e.n * esize);
         it.flags = (int *)off;
         off = a256(off + (size_t)it.tiles * it.npass * sizeof(int));
+        it.status = (int *)(L.status_off + (size_t)i * sizeof(int));
         it.off_negmask = o_neg;
         it.off_parity = o_par;
         it.off_sign = o_sign;
@@ -82,6 +84,7 @@ void batch_rebase(std::vector<BatchItem> &items, uintptr_t base)
         it.parity = (uint8_t *)(base + (uintptr_t)it.parity);
         it.sign = (void *)(base + (uintptr_t)it.sign);
         it.flags = (int *)(base + (uintptr_t)it.flags);
+        it.status = (int *)(base + (uintptr_t)it.status);
     }
 }
 
@@ -261,9 +264,16 @@ int create(int32_t count, const std::vector<Entry> &in, int esize, const rotseq_
     BatchLaunch &L = b->L;
     L.arith = arith;
     L.publish = 1;
-    L.spin_limit = 1 << 22;
+    L.spin_limit = wait_spin_limit();
+    L.wait_bias = wait_bias();
     L.items = (const BatchItem *)b->dmem;
-    L.status = status;
+    (void)status;
+    if (L.count > 0 &&
+        hipMemset((char *)b->dmem + L.status_off, 0, (size_t)L.count * sizeof(int)) != hipSuccess) {
+        (void)hipFree(b->dmem);
+        delete b;
+        return ROTSEQ_E_HIP;
+    }
     int waves = opts && opts->waves > 0 ? opts->waves : kDefaultWaves;
     rc = ROTSEQ_E_UNSUPPORTED;
     while (waves >= 1 && (rc = set_waves(b, waves)) == ROTSEQ_E_UNSUPPORTED)
@@ -288,6 +298,8 @@ int execute(rotseq_batch *b, hipStream_t stream)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
         return ROTSEQ_E_UNSUPPORTED;
+    b->L.spin_limit = wait_spin_limit();
+    b->L.wait_bias = wait_bias();
     if (launch_prep_batch(b->L, stream) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (launch_chain_batch(b->L, stream) != hipSuccess)
@@ -367,6 +379,26 @@ int update_typed(rotseq_batch *b, int32_t count, const P *probs, int esize)
     return update(b, count, in, esize);
 }
 
+// Reads the items' error words (device synchronized first) into `per_item`
+// (dispatch order) and returns their OR; `reset` zeroes them afterwards.
+int read_status(rotseq_batch *b, std::vector<int> &per_item, int reset)
+{
+    per_item.assign((size_t)b->L.count, 0);
+    if (b->L.count == 0)
+        return ROTSEQ_SUCCESS;
+    char *words = (char *)b->dmem + b->L.status_off;
+    const size_t bytes = (size_t)b->L.count * sizeof(int);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(per_item.data(), words, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+        return -ROTSEQ_E_HIP;
+    if (reset && (hipMemset(words, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+        return -ROTSEQ_E_HIP;
+    int any = 0;
+    for (int v : per_item)
+        any |= v;
+    return any;
+}
+
 template <typename P>
 int one_shot(int32_t count, const P *probs, hipStream_t stream, int esize)
 {
@@ -377,6 +409,15 @@ int one_shot(int32_t count, const P *probs, hipStream_t stream, int esize)
     rc = execute(b, stream);
     if (hipStreamSynchronize(stream) != hipSuccess && rc == ROTSEQ_SUCCESS)
         rc = ROTSEQ_E_HIP;
+    if (rc == ROTSEQ_SUCCESS) {
+        // A bounded wait that gave up leaves wrong results: report it.
+        std::vector<int> words;
+        const int any = read_status(b, words, 0);
+        if (any < 0)
+            rc = -any;
+        else if (any != 0)
+            rc = ROTSEQ_E_TIMEOUT;
+    }
     (void)hipFree(b->dmem);
     delete b;
     return rc;
@@ -450,6 +491,23 @@ int rotseq_batch_tune(rotseq_batch *b, hipStream_t stream, int32_t reps)
     (void)hipEventDestroy(e1);
     const int rc2 = set_waves(b, best_waves);
     return rc ? rc : rc2;
+}
+
+int rotseq_batch_status(rotseq_batch *b, int32_t *per_problem, int reset)
+{
+    if (b == nullptr)
+        return -1;
+    std::vector<int> words;
+    const int any = read_status(b, words, reset);
+    if (any < 0)
+        return -any;
+    if (per_problem) {
+        for (size_t i = 0; i < b->shapes.size() / 3; ++i)
+            per_problem[i] = 0;
+        for (size_t t = 0; t < words.size(); ++t)
+            per_problem[b->order[t]] = words[t] & 0xff;  // ROTSEQ_E_* code
+    }
+    return any ? ROTSEQ_E_TIMEOUT : ROTSEQ_SUCCESS;
 }
 
 int rotseq_batch_info_get(const rotseq_batch *b, rotseq_batch_info *info)

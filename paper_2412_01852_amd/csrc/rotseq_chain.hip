@@ -83,6 +83,7 @@ struct ChainArgs {
     int remap;       // 1: consecutive workgroups on the same XCD
     int publish;     // columns (a power of 2) between cross-workgroup progress updates
     int spin_limit;  // polls before a wait gives up
+    int wait_bias;   // added to every flag wait's target (0; a test hook)
     uint32_t lds_words;  // dynamic LDS size in 4-byte words
     uint64_t coef;   // [nbands][steps + 1 + 8][K] coefficient pairs
     uint64_t sign;   // [n] final column signs (lifting arithmetic)
@@ -362,7 +363,8 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         if constexpr (IN == kInWait) {
             if (lc + cols > in_known && lc < n) {
                 const int want = lc + cols;
-                in_known = wait_flag(flag_in, (want < n ? want : n) - 1, limit, timed_out);
+                in_known = wait_flag(flag_in, (want < n ? want : n) - 1 + a.wait_bias, limit,
+                                     timed_out);
             }
         }
     };
@@ -656,9 +658,8 @@ __global__ __launch_bounds__(1024) void sweep_chain(ChainArgs a)
 // Workgroups still only wait for lower-numbered ones of their own item.
 struct BatchChainArgs {
     const BatchItem *items;
-    int count, waves, publish, spin_limit;
+    int count, waves, publish, spin_limit, wait_bias;
     uint32_t lds_words;
-    int *status;
 };
 
 template <typename T, int K, int ARITH>
@@ -689,11 +690,12 @@ __global__ __launch_bounds__(1024) void sweep_chain_batch(BatchChainArgs ba)
     a.remap = 0;
     a.publish = ba.publish;
     a.spin_limit = ba.spin_limit;
+    a.wait_bias = ba.wait_bias;
     a.lds_words = ba.lds_words;
     a.coef = (uint64_t)it.coef;
     a.sign = (uint64_t)it.sign;
     a.flags = it.flags;
-    a.status = ba.status;
+    a.status = it.status;
     chain_workgroup<T, K, ARITH>(a, (int)(g - it.off_wg), lds);
 }
 
@@ -713,6 +715,7 @@ hipError_t go_chain(const Plan &p, T *A, const char *ws, hipStream_t st)
     a.remap = p.remap;
     a.publish = p.publish;
     a.spin_limit = p.spin_limit;
+    a.wait_bias = p.wait_bias;
     a.lds_words = (uint32_t)(p.lds_bytes / 4);
     a.coef = (uint64_t)(ws + p.off_coef);
     a.sign = (uint64_t)(ws + p.off_sign);
@@ -731,8 +734,8 @@ hipError_t go_chain_batch(const BatchLaunch &b, hipStream_t st)
     a.waves = b.waves;
     a.publish = b.publish;
     a.spin_limit = b.spin_limit;
+    a.wait_bias = b.wait_bias;
     a.lds_words = (uint32_t)(b.lds_bytes / 4);
-    a.status = b.status;
     sweep_chain_batch<T, K, ARITH><<<(unsigned)b.nwg, b.waves * kWave, b.lds_bytes, st>>>(a);
     return hipGetLastError();
 }

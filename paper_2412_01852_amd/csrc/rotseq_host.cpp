@@ -18,6 +18,15 @@ namespace rotseq {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+namespace {
+constexpr int kDefaultSpinLimit = 1 << 22;
+std::atomic<int> g_spin_limit{kDefaultSpinLimit};
+std::atomic<int> g_wait_bias{0};
+}  // namespace
+
+int wait_spin_limit() { return g_spin_limit.load(std::memory_order_relaxed); }
+int wait_bias() { return g_wait_bias.load(std::memory_order_relaxed); }
+
 bool make_plan(Plan &p, int req_kernel, int req_band)
 {
     // The chain kernel addresses the n column signs with 32-bit byte
@@ -77,9 +86,9 @@ struct DeviceInfo {
     int cus = 0;
     size_t max_lds = 0;
     size_t lds_per_cu = 0;
-    int *status = nullptr;  // sticky device-side error word
 };
 
+// Attributes of the current device (cached; queries only, no allocation).
 int device_info(DeviceInfo &out)
 {
     static std::mutex mu;
@@ -102,15 +111,34 @@ int device_info(DeviceInfo &out)
             hipSuccess)
             return ROTSEQ_E_HIP;
         d.lds_per_cu = (size_t)v;
-        if (hipMalloc(&d.status, sizeof(int)) != hipSuccess)
-            return ROTSEQ_E_NOMEM;
-        if (hipMemset(d.status, 0, sizeof(int)) != hipSuccess)
-            return ROTSEQ_E_HIP;
-        if (hipDeviceSynchronize() != hipSuccess)
-            return ROTSEQ_E_HIP;
         it = cache.emplace(dev, d).first;
     }
     out = it->second;
+    return ROTSEQ_SUCCESS;
+}
+
+// The current device's sticky error word of the plain calls, allocated
+// and zeroed on first use.
+int status_word(int **out)
+{
+    static std::mutex mu;
+    static std::map<int, int *> words;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = words.find(dev);
+    if (it == words.end()) {
+        int *w = nullptr;
+        if (hipMalloc(&w, sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            return ROTSEQ_E_NOMEM;
+        }
+        if (hipMemset(w, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return ROTSEQ_E_HIP;
+        it = words.emplace(dev, w).first;
+    }
+    *out = it->second;
     return ROTSEQ_SUCCESS;
 }
 
@@ -184,8 +212,8 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
     while (pow2 < publish)
         pow2 *= 2;
     p.publish = pow2;
-    p.spin_limit = 1 << 22;
-    p.status = d.status;
+    p.spin_limit = wait_spin_limit();
+    p.wait_bias = wait_bias();
     return hipSuccess;
 }
 
@@ -398,6 +426,8 @@ int run(int kind, int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C
         return ROTSEQ_E_UNSUPPORTED;
     if (configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0) != hipSuccess)
         return ROTSEQ_E_HIP;
+    if (const int rc = status_word(&p.status))
+        return rc;
     if (ws) {
         if (ws_bytes < p.total || ((uintptr_t)ws & 255) != 0)
             return ROTSEQ_E_WORKSPACE;
@@ -531,8 +561,7 @@ int device_query(int *cus, size_t *max_lds, int **status)
         return rc;
     *cus = d.cus;
     *max_lds = d.max_lds;
-    *status = d.status;
-    return ROTSEQ_SUCCESS;
+    return status_word(status);
 }
 
 }  // namespace rotseq
@@ -649,18 +678,29 @@ const char *rotseq_strerror(int code)
 
 int rotseq_version(void) { return 100; }
 
+int rotseq_test_set_waits(int32_t spin_limit, int32_t unreachable)
+{
+    if (spin_limit < 0)
+        return -1;
+    g_spin_limit.store(spin_limit == 0 ? kDefaultSpinLimit : spin_limit, std::memory_order_relaxed);
+    // Column counts are below 2^28 (larger n runs the multipass kernel,
+    // which never waits), so a target 2^29 higher is never reached.
+    g_wait_bias.store(unreachable ? (1 << 29) : 0, std::memory_order_relaxed);
+    return ROTSEQ_SUCCESS;
+}
+
 int rotseq_device_status(int reset)
 {
-    DeviceInfo d;
-    const int rc = device_info(d);
+    int *word = nullptr;
+    const int rc = status_word(&word);
     if (rc)
         return rc;
     if (hipDeviceSynchronize() != hipSuccess)
         return ROTSEQ_E_HIP;
     int v = 0;
-    if (hipMemcpy(&v, d.status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(&v, word, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return ROTSEQ_E_HIP;
-    if (reset && hipMemset(d.status, 0, sizeof(int)) != hipSuccess)
+    if (reset && hipMemset(word, 0, sizeof(int)) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (reset && hipDeviceSynchronize() != hipSuccess)
         return ROTSEQ_E_HIP;

@@ -49,7 +49,7 @@ struct Plan {
     int kind;    // Kind
     int esize;   // sizeof element: 8 (double) or 4 (float)
     // Launch shape of the chain kernel (configure_launch).
-    int waves, nwg, remap, publish, spin_limit;
+    int waves, nwg, remap, publish, spin_limit, wait_bias;
     size_t lds_bytes;
     int *status;  // sticky device error word (ROTSEQ_E_* bits)
     // Workspace layout (byte offsets from the workspace base, 256-aligned).
@@ -70,17 +70,18 @@ struct BatchItem {
     void *sign;  // T[n]
     void *coef;  // CoefPair<T>[npass * (steps + pad) * band]
     int *flags;  // int[tiles * npass]
+    int *status; // this item's error word (ROTSEQ_E_* bits of its waits)
     int64_t off_negmask, off_parity, off_sign, off_coef, off_flags, off_wg;
 };
 
 // Launch parameters shared by all items of a batch.
 struct BatchLaunch {
     int count;         // items
-    int esize, arith, band, waves, publish, spin_limit;
+    int esize, arith, band, waves, publish, spin_limit, wait_bias;
     size_t lds_bytes;
     int64_t total_negmask, total_parity, total_sign, total_coef, total_flags, nwg;
     const BatchItem *items;  // device copy, `count` entries
-    int *status;
+    size_t status_off;       // byte offset of the items' error words in the block
 };
 
 // One problem of a batch before layout (all fields as in rotseq_d).
@@ -90,9 +91,10 @@ struct BatchEntry {
     int64_t m, n, k, lda, ldc, lds;
 };
 // Lays out a batch in the given order: fills `items` and the totals of `L`
-// (count, band, esize, total_*); every device pointer of an item is an
-// offset from the start of one device block whose first bytes hold the item
-// table.  Returns the block's size.  Host-only.
+// (count, band, esize, total_*, status_off); every device pointer of an item
+// is an offset from the start of one device block whose first bytes hold the
+// item table, followed by one error word per item (status_off; the owner
+// zeroes them).  Returns the block's size.  Host-only.
 size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
                     std::vector<BatchItem> &items, BatchLaunch &L);
 // Turns the offsets of batch_layout into addresses inside the block at `base`.
@@ -111,6 +113,12 @@ hipError_t launch_chain_batch(const BatchLaunch &b, hipStream_t stream);
 // workspace offsets) from its shape and the requested kernel and band
 // (0 = auto).  Returns false for unsupported requests.  Host-only.
 bool make_plan(Plan &p, int req_kernel, int req_band);
+
+// Polls before a wait between workgroups gives up, and the amount added to
+// every such wait's target (0, or past any column count, so that every wait
+// gives up: a test hook for the error path); set by rotseq_test_set_waits.
+int wait_spin_limit();
+int wait_bias();
 
 // Fills the launch shape of `p` for the current device (queries its CU count
 // and occupancy).  `req_waves` > 0 forces the waves per workgroup.

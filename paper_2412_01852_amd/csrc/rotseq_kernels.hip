@@ -29,88 +29,17 @@
 
 #include <algorithm>
 
+#include "rotseq.h"
+#include "rotseq_device.h"
 #include "rotseq_internal.h"
 
 namespace rotseq {
 namespace {
 
-constexpr int kWave = 64;
-// Dword 3 of a gfx9-family buffer descriptor: 32-bit data format, no swizzle.
-constexpr int kRsrcWord3 = 0x00020000;
-// Cache policy for loads of A: SC0 set, i.e. served coherently from L2 (the
-// CU's L1 may hold a stale copy of a column written by the previous band).
-constexpr int kLoadCoherent = 1;
+using namespace dev;
+
 // Wavefront steps a column load is issued ahead of its first use.
 constexpr int kPrefetch = 4;
-
-template <typename T>
-struct CoefPair {
-    T a, b;
-};
-
-// Address space 4 (constant): uniform loads through these pointers become
-// scalar loads into SGPRs.
-template <typename T>
-using ConstPairs = const __attribute__((address_space(4))) CoefPair<T> *;
-template <typename T>
-using ConstScalars = const __attribute__((address_space(4))) T *;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, bytes, kRsrcWord3);
-}
-
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ double buf_load(double, __amdgpu_buffer_rsrc_t r, int voff)
-{
-    u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, kLoadCoherent);
-    return __builtin_bit_cast(double, v);
-}
-__device__ __forceinline__ float buf_load(float, __amdgpu_buffer_rsrc_t r, int voff)
-{
-    unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, kLoadCoherent);
-    return __builtin_bit_cast(float, v);
-}
-__device__ __forceinline__ void buf_store(double x, __amdgpu_buffer_rsrc_t r, int voff)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, voff, 0, 0);
-}
-__device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, int voff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, 0, 0);
-}
-
-// Keeps a running scalar address opaque to loop strength reduction, which
-// would otherwise turn each unrolled step's address into its own 64-bit
-// induction variable and exhaust the SGPR file.  Emits no instruction.
-__device__ __forceinline__ void opaque(uint64_t &x) { asm volatile("" : "+s"(x)); }
-
-__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// One rotation of the entries (x, y) of a row; (a, b) as prepared by prep_coef.
-template <int ARITH, typename T>
-__device__ __forceinline__ void rotate(T &x, T &y, T a, T b)
-{
-    if constexpr (ARITH == kExact) {
-        // Algorithm 1 as written: (a, b) = (c, s), every product and sum
-        // rounded separately.
-#pragma clang fp contract(off)
-        T t = a * x + b * y;
-        y = -b * x + a * y;
-        x = t;
-    } else if constexpr (ARITH == kFma) {
-        T t = fmad(a, x, b * y);
-        y = fmad(a, y, -(b * x));
-        x = t;
-    } else {
-        // Lifting form, (a, b) = (s'/(1+c'), -s') with c' >= 0.
-        x = fmad(a, y, x);
-        y = fmad(b, x, y);
-        x = fmad(a, y, x);
-    }
-}
 
 // One band of K sequences over the whole tile: steps t = 0 .. steps-1.
 // `tile` is the address of A(i0, 0), `ldab` the column stride in bytes.
@@ -129,7 +58,7 @@ __device__ __forceinline__ void sweep_band(uint64_t tile, uint64_t ldab, uint32_
     int lc = 0;
 #pragma unroll
     for (int c = 0; c <= D; ++c) {
-        ring[c] = buf_load(T(), make_rsrc((const void *)lp, lc < n ? rowbytes : 0u), voff);
+        ring[c] = buf_load<kPolicyL2>(T(), make_rsrc(lp, lc < n ? rowbytes : 0u), voff);
         lp += ldab;
         ++lc;
         opaque(lp);
@@ -143,7 +72,7 @@ __device__ __forceinline__ void sweep_band(uint64_t tile, uint64_t ldab, uint32_
         for (int u = 0; u < R; ++u) {
             // Column t+1+D goes into the slot of column t-K, stored last step.
             ring[(u + D + 1) % R] =
-                buf_load(T(), make_rsrc((const void *)lp, lc < n ? rowbytes : 0u), voff);
+                buf_load<kPolicyL2>(T(), make_rsrc(lp, lc < n ? rowbytes : 0u), voff);
             lp += ldab;
             ++lc;
             opaque(lp);
@@ -160,7 +89,7 @@ __device__ __forceinline__ void sweep_band(uint64_t tile, uint64_t ldab, uint32_
             const bool valid = (unsigned)sc < (unsigned)n;
             if constexpr (SIGN)
                 v *= sign[valid ? sc : 0];
-            buf_store(v, make_rsrc((const void *)sp, valid ? rowbytes : 0u), voff);
+            buf_store(v, make_rsrc(sp, valid ? rowbytes : 0u), voff);
             sp += ldab;
             ++sc;
             opaque(sp);
@@ -248,21 +177,32 @@ __device__ __forceinline__ void pair_rotation(int kind, T cv, T sv, double &c, d
 
 // negmask[pass*(n-1) + j]: bit q = pair (j, pass*K + q) negates column j,
 // bit 32 + q = it negates column j+1 (K <= 32).
+// `nonortho` is set when a reflector (tau, nu) with tau != 0 is not
+// orthogonal, |tau (1 + nu^2) - 2| > 64 eps(T): the rotation-plus-negation
+// form applies only to orthogonal reflectors (Section 6 counts the work of
+// H = I - tau v v^T as a replacement for a rotation).
 template <typename T>
 __device__ __forceinline__ uint64_t negmask_elem(const T *__restrict__ C, int64_t cj, int64_t ldc,
                                                  const T *__restrict__ S, int64_t lds, int64_t n1,
-                                                 int64_t k, int K, int kind, int64_t idx)
+                                                 int64_t k, int K, int kind, int64_t idx,
+                                                 bool &nonortho)
 {
+    constexpr double kTol = 64.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
     const int64_t pass = idx / n1, j = idx - pass * n1;
     uint64_t mask = 0;
     for (int q = 0; q < K; ++q) {
         const int64_t p = pass * K + q;
         if (p >= k)
             continue;
+        const T cv = C[j * cj + p * ldc];
+        const T sv = kind == kRotate ? T(0) : S[j * cj + p * lds];
         double c, s;
         bool flip;
-        pair_rotation(kind, C[j * cj + p * ldc], kind == kRotate ? T(0) : S[j * cj + p * lds], c, s,
-                      flip);
+        pair_rotation(kind, cv, sv, c, s, flip);
+        if (kind != kRotate && cv != T(0)) {
+            const double nu = (double)sv;
+            nonortho |= !(__builtin_fabs((double)cv * (1.0 + nu * nu) - 2.0) <= kTol);
+        }
         const uint64_t neg = c < 0.0 ? 1u : 0u;
         mask |= (neg << q) | ((neg ^ (flip ? 1u : 0u)) << (32 + q));
     }
@@ -351,12 +291,16 @@ __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_
 template <typename T>
 __global__ void prep_negmask(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
                              int64_t lds, int64_t n1, int64_t k, int K, int npass, int kind,
-                             uint64_t *__restrict__ negmask)
+                             uint64_t *__restrict__ negmask, int *status)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)npass * n1)
         return;
-    negmask[idx] = negmask_elem(C, cj, ldc, S, lds, n1, k, K, kind, idx);
+    bool nonortho = false;
+    negmask[idx] = negmask_elem(C, cj, ldc, S, lds, n1, k, K, kind, idx, nonortho);
+    if (nonortho)
+        __hip_atomic_fetch_or(status, ROTSEQ_STATUS_NOT_ORTHOGONAL, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
@@ -507,9 +451,11 @@ __global__ void prep_batch(const BatchItem *__restrict__ items, int count, int64
     const BatchItem &it = items[item];
     const int64_t i = idx - stage_off<STAGE>(it);
     const int64_t n1 = it.n - 1;
-    if constexpr (STAGE == kStageNegmask)
+    if constexpr (STAGE == kStageNegmask) {
+        bool unused = false;  // rotations only
         it.negmask[i] = negmask_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1, it.k, K,
-                                     kRotate, i);
+                                     kRotate, i, unused);
+    }
     else if constexpr (STAGE == kStageParity)
         parity_elem(it.negmask, n1, it.npass, it.parity, i);
     else if constexpr (STAGE == kStageSign)
@@ -535,7 +481,7 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
     constexpr int B = 256;
     if (p.arith == kLift) {
         prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(
-            C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band, p.npass, p.kind, negmask);
+            C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band, p.npass, p.kind, negmask, p.status);
         prep_parity<<<blocks_for(n1, B), B, 0, st>>>(negmask, n1, p.npass, parity);
         prep_sign<T><<<blocks_for(p.n, B), B, 0, st>>>(parity + (int64_t)p.npass * n1, p.n, sign);
     }

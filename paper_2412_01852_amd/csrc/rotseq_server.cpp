@@ -121,8 +121,10 @@ struct InFlight {
 struct Arena {
     void *dev = nullptr;
     size_t bytes = 0;
-    void *table = nullptr;  // pinned item table
+    void *table = nullptr;  // pinned item table, then zeroed error words
     size_t table_bytes = 0;
+    int *words = nullptr;   // pinned copy of the items' error words after the batch
+    size_t words_cap = 0;   // entries
 };
 
 }  // namespace
@@ -355,7 +357,20 @@ int launch(rotseq_server *s, InFlight &f)
         }
         ar.bytes = want;
     }
-    const size_t table = items.size() * sizeof(BatchItem);
+    // The item table and the items' zeroed error words are one upload.
+    const size_t table = L.status_off + (size_t)count * sizeof(int);
+    if (ar.words_cap < (size_t)count) {
+        if (ar.words)
+            (void)hipHostFree(ar.words);
+        ar.words = nullptr;
+        ar.words_cap = 0;
+        if (hipHostMalloc((void **)&ar.words, (size_t)count * 2 * sizeof(int), hipHostMallocDefault) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return ROTSEQ_E_NOMEM;
+        }
+        ar.words_cap = (size_t)count * 2;
+    }
     if (ar.table_bytes < table) {
         if (ar.table)
             (void)hipHostFree(ar.table);
@@ -375,8 +390,8 @@ int launch(rotseq_server *s, InFlight &f)
     batch_rebase(items, base + cs_region);
     L.arith = kLift;
     L.publish = 1;
-    L.spin_limit = 1 << 22;
-    L.status = s->status;
+    L.spin_limit = wait_spin_limit();
+    L.wait_bias = wait_bias();
     L.items = (const BatchItem *)(base + cs_region);
     int waves = 8;
     size_t lds = chain_lds_bytes(8, waves, 8);
@@ -385,7 +400,8 @@ int launch(rotseq_server *s, InFlight &f)
     L.waves = waves;
     L.lds_bytes = lds;
     L.nwg = batch_assign_workgroups(items, waves);
-    std::memcpy(ar.table, items.data(), table);
+    std::memcpy(ar.table, items.data(), items.size() * sizeof(BatchItem));
+    std::memset((char *)ar.table + L.status_off, 0, (size_t)count * sizeof(int));
     // Uploads on the upload stream; the previous use of this arena slot has
     // completed (its batch was retired before the slot was reused).
     off = 0;
@@ -403,21 +419,33 @@ int launch(rotseq_server *s, InFlight &f)
         return ROTSEQ_E_HIP;
     if (launch_prep_batch(L, s->comp) != hipSuccess || launch_chain_batch(L, s->comp) != hipSuccess)
         return ROTSEQ_E_HIP;
+    // The items' error words come back with the batch (read in retire).
+    if (hipMemcpyAsync(ar.words, (const char *)L.items + L.status_off, (size_t)count * sizeof(int),
+                       hipMemcpyDeviceToHost, s->comp) != hipSuccess)
+        return ROTSEQ_E_HIP;
     if (hipEventRecord(f.done, s->comp) != hipSuccess)
         return ROTSEQ_E_HIP;
     return ROTSEQ_SUCCESS;
 }
 
+// Finishes the sweeps of a batch: `rc` for all of them if the launch or the
+// wait failed, else each sweep's own error word (a bounded wait of its
+// kernel that gave up leaves its matrix wrong: ROTSEQ_E_TIMEOUT).  A failed
+// sweep fails the later sweeps of its matrix.
 void retire(rotseq_server *s, InFlight &f, int rc)
 {
     if (rc == ROTSEQ_SUCCESS && hipEventSynchronize(f.done) != hipSuccess)
         rc = ROTSEQ_E_HIP;
+    const int *words = rc == ROTSEQ_SUCCESS ? s->arena[f.slot].words : nullptr;
     std::lock_guard<std::mutex> lock(s->mu);
     const double at = now_us(s);
     for (size_t i = 0; i < f.tasks.size(); ++i) {
-        finish(s, f.tasks[i], rc, at);
+        int st = rc;
+        if (words && words[i] != 0)
+            st = ROTSEQ_E_TIMEOUT;
+        finish(s, f.tasks[i], st, at);
         f.mats[i]->inflight = false;
-        if (rc)
+        if (st)
             f.mats[i]->failed = true;
         run_host_heads(s, f.mats[i]);
     }
@@ -807,6 +835,8 @@ int rotseq_server_destroy(rotseq_server *s)
             (void)hipFree(a.dev);
         if (a.table)
             (void)hipHostFree(a.table);
+        if (a.words)
+            (void)hipHostFree(a.words);
     }
     if (s->comp)
         (void)hipStreamSynchronize(s->comp);

@@ -142,7 +142,17 @@ def test_batch_null_handles_are_rejected():
     assert lib.rotseq_batch_execute(None, None) == -1
     assert lib.rotseq_batch_tune(None, None, 3) == -1
     assert lib.rotseq_batch_info_get(None, None) == -1
+    assert lib.rotseq_batch_status(None, None, 0) == -1
     assert lib.rotseq_batch_destroy(None) == 0
+
+
+def test_wait_hook_argument_check_and_reset():
+    """rotseq_test_set_waits refuses a negative limit and restores the
+    defaults with (0, 0); host-only (it sets values later launches read)."""
+    lib = rs._lib._load()
+    assert lib.rotseq_test_set_waits(-1, 0) == -1
+    assert lib.rotseq_test_set_waits(1, 1) == 0
+    assert lib.rotseq_test_set_waits(0, 0) == 0
 
 
 def test_server_argument_checks_without_device():

@@ -48,8 +48,12 @@ def oracle_full(pb, dtype, times=1):
     return np.asarray(ref)
 
 
-def check_status():
+def check_status(*batches):
+    """No bounded wait gave up: in the device word (plain calls) or in the
+    plans' own words (batches)."""
     assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+    for b in batches:
+        assert b.status() == (0, [0] * len(b._keep)), "a wait of the batch timed out"
 
 
 @pytest.mark.parametrize("arith", ["lift", "exact", "fma"])
@@ -65,7 +69,7 @@ def test_batch_mixed_fp64(arith, waves):
         assert info["count"] == sum(1 for (m, n, k, _) in MIXED if m > 0 and n > 1 and k > 0)
         b.execute()
         torch.cuda.synchronize()
-    check_status()
+        check_status(b)
     for pb, (A, _, _) in zip(pbs, dev):
         got = rs.host_colmajor(A)
         ref = oracle_full(pb, "f64")
@@ -83,11 +87,16 @@ def test_batch_bitwise_equals_single_calls(band):
     pbs = mixed_problems(seed=40)
     dev_b = upload(pbs, "f64")
     dev_s = upload(pbs, "f64")
-    rs.batched(dev_b) if band == 8 else rs.Batch(dev_b, {"band": band}).execute()
+    plans = []
+    if band == 8:
+        rs.batched(dev_b)  # raises on a time-out
+    else:
+        plans.append(rs.Batch(dev_b, {"band": band}))
+        plans[0].execute()
     for A, C, S in dev_s:
         rs.rotseq(A, C, S, opts={"kernel": rs.KERNEL_CHAIN, "band": band})
     torch.cuda.synchronize()
-    check_status()
+    check_status(*plans)
     for (Ab, _, _), (As, _, _) in zip(dev_b, dev_s):
         assert torch.equal(Ab, As)
 
@@ -114,7 +123,7 @@ def test_batch_execute_twice_and_tune():
         b.execute()
         b.execute()
         torch.cuda.synchronize()
-        check_status()
+        check_status(b)
         for pb, (A, _, _) in zip(pbs, dev):
             assert relerr(rs.host_colmajor(A), oracle_full(pb, "f64", times=2), pb.A) <= 2 * TOL["f64"]
         b.tune(reps=1)
@@ -122,7 +131,7 @@ def test_batch_execute_twice_and_tune():
         before = [rs.host_colmajor(A) for A, _, _ in dev]
         b.execute()
         torch.cuda.synchronize()
-        check_status()
+        check_status(b)
         for before_i, pb, (A, _, _) in zip(before, pbs, dev):
             ref = oracle.colmajor(before_i)
             oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
@@ -153,7 +162,7 @@ def test_batch_graph_replays_match_eager():
         junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
         be.execute()
         torch.cuda.synchronize()
-        check_status()
+        check_status(bg, be)
         float(junk)
         for (Ag, _, _), (Ae, _, _) in zip(dev_g, dev_e):
             assert torch.equal(Ag, Ae), f"replay {r} differs from eager execution"
@@ -174,7 +183,7 @@ def test_uneven_512_batch_sampled():
         assert info["count"] == 512
         b.execute()
         torch.cuda.synchronize()
-    check_status()
+        check_status(b)
     rng = np.random.default_rng(0)
     pick = set(rng.choice(512, 24, replace=False).tolist())
     for i, (pb, (A, _, _)) in enumerate(zip(pbs, dev)):
@@ -203,7 +212,7 @@ def test_batch_update_pointers():
     b.update(dev2)
     b.execute()
     torch.cuda.synchronize()
-    check_status()
+    check_status(b)
     for pb, (A, _, _) in zip(pbs1, dev1):
         assert relerr(rs.host_colmajor(A), oracle_full(pb, "f64"), pb.A) <= TOL["f64"]
     for pb, (A, _, _) in zip(pbs2, dev2):
@@ -228,7 +237,7 @@ def test_batch_update_pointers():
     b.update(dev4)
     g.replay()
     torch.cuda.synchronize()
-    check_status()
+    check_status(b)
     for pb, (A, _, _) in zip(pbs2, dev4):
         assert relerr(rs.host_colmajor(A), oracle_full(pb, "f64"), pb.A) <= TOL["f64"]
     for pb, (A, _, _) in zip(pbs1, dev3):  # untouched by the replay after the update

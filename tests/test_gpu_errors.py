@@ -1,0 +1,162 @@
+"""Error paths on the GPU, forced from the host so that every kernel still
+runs to completion:
+
+- a bounded wait between workgroups that gives up (rotseq_test_set_waits
+  with `unreachable`: every such wait asks for a column count no producer
+  reaches, and gives up after one poll) must surface as ROTSEQ_E_TIMEOUT:
+  in the device status word after a plain call, as the return code of the
+  one-shot batch, per entry in a plan's status words, and in the ticket of
+  the served sweep, whose matrix then fails its later sweeps;
+- a 2x2 reflector that is not orthogonal must set
+  ROTSEQ_STATUS_NOT_ORTHOGONAL in the device status word.
+
+Chains cross workgroups only where a tile has more bands than a workgroup
+has waves, so the shapes below force that (and include entries that do not
+cross, which must stay clean).
+"""
+import numpy as np
+import pytest
+
+import paper_2412_01852_amd as rs
+from paper_2412_01852_amd.inputs import make_cs, make_problem, make_refl_problem
+from gpu_util import TOL, relerr, say, to_dev
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+E_TIMEOUT, E_FAILED = 5, 9
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture
+def unreachable_waits():
+    import torch
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
+    rs.test_set_waits(1, unreachable=True)
+    try:
+        yield
+    finally:
+        torch.cuda.synchronize()
+        rs.test_set_waits(0, unreachable=False)
+        rs.device_status(reset=True)
+
+
+def _dev(pb):
+    return to_dev(pb.A, "f64"), to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+
+
+def test_plain_call_reports_timeout(unreachable_waits):
+    """8 bands of 8 over 2 workgroups of 4 waves per tile: the second
+    workgroup's waits give up and the status word says so."""
+    say("errors: plain call, forced wait time-out")
+    import torch
+    A, C, S = _dev(make_problem(130, 300, 64, seed=401))
+    rs.rotseq(A, C, S, opts={"waves": 4})
+    torch.cuda.synchronize()
+    st = rs.device_status(reset=True)
+    assert st & 0xff == E_TIMEOUT, hex(st)
+    assert rs.device_status(reset=True) == 0
+
+
+def test_plain_call_single_workgroup_chain_stays_clean(unreachable_waits):
+    """A chain inside one workgroup never waits on another: no time-out."""
+    say("errors: plain call without cross-workgroup waits")
+    import torch
+    pb = make_problem(130, 300, 64, seed=402)
+    A, C, S = _dev(pb)
+    rs.rotseq(A, C, S, opts={"waves": 8})
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
+    ref = oracle.colmajor(np.asarray(pb.A))
+    oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
+    assert relerr(rs.host_colmajor(A), np.asarray(ref), pb.A) <= TOL["f64"]
+
+
+def test_one_shot_batch_returns_timeout(unreachable_waits):
+    say("errors: one-shot batch, forced wait time-out")
+    # k = 128 is 16 bands of 8, more than the plan's default 8 waves
+    items = [_dev(make_problem(100, 200, 128, seed=403)), _dev(make_problem(64, 50, 8, seed=404))]
+    with pytest.raises(rs.RotseqError) as e:
+        rs.batched(items)
+    assert e.value.code == E_TIMEOUT
+
+
+def test_batch_plan_status_per_entry(unreachable_waits):
+    """Only the entry whose chains cross workgroups is flagged; the other
+    entry's result is still right."""
+    say("errors: batch plan status words")
+    import torch
+    pbs = [make_problem(64, 50, 8, seed=405), make_problem(100, 200, 128, seed=406),
+           make_problem(70, 33, 16, seed=407)]
+    items = [_dev(pb) for pb in pbs]
+    with rs.Batch(items) as b:
+        b.execute()
+        torch.cuda.synchronize()
+        rc, per = b.status()
+        assert rc == E_TIMEOUT and per == [0, E_TIMEOUT, 0], per
+        # sticky until reset
+        rc, per = b.status(reset=True)
+        assert per == [0, E_TIMEOUT, 0]
+        assert b.status() == (0, [0, 0, 0])
+    for i in (0, 2):
+        ref = oracle.colmajor(np.asarray(pbs[i].A))
+        oracle.rotseq(ref, oracle.colmajor(pbs[i].C), oracle.colmajor(pbs[i].S))
+        assert relerr(rs.host_colmajor(items[i][0]), np.asarray(ref), pbs[i].A) <= TOL["f64"]
+
+
+def test_server_ticket_reports_timeout_and_fails_later_sweeps(unreachable_waits):
+    """The served sweep whose kernel gave up a wait reports ROTSEQ_E_TIMEOUT,
+    the matrix's later sweeps ROTSEQ_E_FAILED; a matrix batched with it
+    whose chains stay in one workgroup completes correctly."""
+    say("errors: server, forced wait time-out")
+    rng = np.random.default_rng(408)
+    bad = make_problem(100, 200, 1, seed=409)
+    good = make_problem(90, 60, 1, seed=410)
+    bad_sweeps = [make_cs(bad.n, 128, rng) for _ in range(2)]  # 16 bands > 8 waves
+    good_sweeps = [make_cs(good.n, 8, rng) for _ in range(2)]  # one band
+    with rs.Server() as srv:
+        mb, mg = srv.open(bad.A), srv.open(good.A)
+        tb = [srv.submit(mb, C, S) for C, S in bad_sweeps]
+        tg = [srv.submit(mg, C, S) for C, S in good_sweeps]
+        assert [srv.wait(t)[0] for t in tb] == [E_TIMEOUT, E_FAILED]
+        assert [srv.wait(t)[0] for t in tg] == [0, 0]
+        with pytest.raises(rs.RotseqError) as e:
+            srv.read(mb, bad.m, bad.n)
+        assert e.value.code == E_FAILED
+        got = srv.read(mg, good.m, good.n)
+        st = srv.stats()
+        assert st["sweeps_failed"] == 2 and st["sweeps_done"] == 2
+    ref = oracle.colmajor(np.asarray(good.A))
+    for C, S in good_sweeps:
+        oracle.rotseq(ref, oracle.colmajor(C), oracle.colmajor(S))
+    assert relerr(got, np.asarray(ref), good.A) <= TOL["f64"]
+
+
+def test_non_orthogonal_reflector_sets_status():
+    say("errors: non-orthogonal 2x2 reflector")
+    import torch
+    assert rs.device_status(reset=True) == 0
+    pb = make_refl_problem(70, 40, 6, seed=411)
+    TAU = np.array(pb.C, copy=True, order="F")
+    TAU[5, 3] = 1.5 if TAU[5, 3] == 0.0 else TAU[5, 3] * 1.01
+    A = to_dev(pb.A, "f64")
+    rs.reflseq(A, to_dev(oracle.colmajor(TAU), "f64"), to_dev(pb.S, "f64"))
+    torch.cuda.synchronize()
+    st = rs.device_status(reset=True)
+    assert st == rs.STATUS_NOT_ORTHOGONAL, hex(st)
+    # orthogonal ones (and tau = 0) leave it clean, in FP32 as well
+    for dt in ("f64", "f32"):
+        A = to_dev(pb.A, dt)
+        rs.reflseq(A, to_dev(pb.C, dt), to_dev(pb.S, dt))
+        torch.cuda.synchronize()
+        assert rs.device_status(reset=True) == 0, dt

@@ -6,6 +6,8 @@ arithmetic mode (Algorithm 1 without fused multiply-adds) must be bitwise.
 Large shapes are checked on sampled rows, which the oracle computes alone
 because rows of A never interact.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -156,25 +158,70 @@ def run_sampled(m, n, k, seed, dtype, opts=None):
     return relerr(got, ref, a0), drift
 
 
+def oracle_threads():
+    """Host threads for the full-size oracle: the CPU share of one GPU."""
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def run_full_large(m, n, k, seed, dtype):
+    """The default call (the bench's launch configuration) on a full-size
+    problem, compared element by element with the threaded oracle (bitwise
+    equal to the serial one: rows never interact).  Returns the relative
+    error and the largest relative change of a row norm."""
+    import torch
+    pb = make_problem(m, n, k, seed=seed)
+    A = to_dev(pb.A, dtype)
+    C = to_dev(pb.C, dtype)
+    S = to_dev(pb.S, dtype)
+    norms0 = torch.linalg.vector_norm(A.double(), dim=1)
+    rs.rotseq(A, C, S)
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+    norms1 = torch.linalg.vector_norm(A.double(), dim=1)
+    drift = float(torch.max(torch.abs(norms1 - norms0) / norms0))
+    got = rs.host_colmajor(A)
+    del A
+    a0 = widened(pb.A, dtype)
+    ref = oracle.colmajor(a0)
+    oracle.rotseq(ref, oracle.colmajor(widened(pb.C, dtype)), oracle.colmajor(widened(pb.S, dtype)),
+                  threads=oracle_threads())
+    return relerr(got, np.asarray(ref), a0), drift
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("kernel", ["chain", "multipass"])
-def test_target_10240_k192_sampled(dtype, kernel):
-    """m = n = 10240, k = 192: sampled rows against the oracle; every row's
-    norm is preserved (an orthogonal transform)."""
-    say(f"target 10240x10240 k=192 {dtype} kernel={kernel} (sampled rows)")
-    kern = rs.KERNEL_CHAIN if kernel == "chain" else rs.KERNEL_MULTIPASS
-    err, drift = run_sampled(10240, 10240, 192, 2, dtype, {"kernel": kern})
+def test_target_10240_k192_full(dtype):
+    """m = n = 10240, k = 192 in the default launch: every element against
+    the oracle; every row's norm is preserved (an orthogonal transform)."""
+    say(f"target 10240x10240 k=192 {dtype} (all elements)")
+    err, drift = run_full_large(10240, 10240, 192, 2, dtype)
     say(f"  rel err {err:.3e}  max row-norm drift {drift:.3e}")
     assert err <= TOL[dtype]
     assert drift <= (1e-12 if dtype == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_target_10240_k192_multipass_sampled(dtype):
+    """The multipass kernel at the target size on sampled rows."""
+    say(f"target 10240x10240 k=192 {dtype} kernel=multipass (sampled rows)")
+    err, drift = run_sampled(10240, 10240, 192, 2, dtype, {"kernel": rs.KERNEL_MULTIPASS})
+    say(f"  rel err {err:.3e}  max row-norm drift {drift:.3e}")
+    assert err <= TOL[dtype]
+    assert drift <= (1e-12 if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("k", [1, 8, 32, 128])
-def test_tall_32768x4096_sampled(k):
-    say(f"tall 32768x4096 k={k} fp64 (sampled rows)")
-    err, drift = run_sampled(32768, 4096, k, 3 + k, "f64")
-    say(f"  rel err {err:.3e}")
-    assert err <= TOL["f64"]
+def test_tall_32768x4096_full(k, dtype):
+    """The tall configuration (memory-bound to compute-bound as k grows) in
+    the default launch, every element against the oracle."""
+    say(f"tall 32768x4096 k={k} {dtype} (all elements)")
+    err, drift = run_full_large(32768, 4096, k, 3 + k, dtype)
+    say(f"  rel err {err:.3e}  max row-norm drift {drift:.3e}")
+    assert err <= TOL[dtype]
+    assert drift <= (1e-12 if dtype == "f64" else 1e-4)
 
 
 def test_caller_workspace_and_stream():

@@ -130,3 +130,45 @@ def test_server_alone_equals_amid_traffic():
         assert srv.stats()["mean_batch"] > 1.0
     assert np.array_equal(alone, amid)
     assert relerr(alone, oracle_sweeps(pb.A, plan), pb.A) <= 5 * TOL["f64"]
+
+
+def test_served_scale_requests_sampled_rows():
+    """Requests of the served configuration at its own scale: n log-uniform
+    in [128, 4096] (the largest drawn ones plus n = 4096 itself), k per
+    request in {16, 32, 64, 128}, 20 sweeps each with fresh angles, all
+    resident at once and batched together.  Every row's norm is kept, and
+    sampled rows match the oracle applied sweep by sweep (rows are
+    independent, so the oracle runs on those rows alone)."""
+    from paper_2412_01852_amd.inputs import request_matrix, served_requests
+    reqs = served_requests(48, seed=5)
+    reqs = sorted(reqs, key=lambda r: -r["n"])[:3] + reqs[-3:]
+    reqs.append(dict(reqs[0], m=4096, n=4096, k=128))
+    say("server at served scale: " + ", ".join(f"n={r['n']} k={r['k']}" for r in reqs))
+    work = []
+    for r in reqs:
+        A, rng = request_matrix(r)
+        sweeps = [make_cs(r["n"], r["k"], rng) for _ in range(r["sweeps"])]
+        work.append((A, sweeps))
+    with rs.Server() as srv:
+        ids = [srv.open(A) for A, _ in work]
+        tickets = []
+        for s in range(20):
+            for mid, (_, sweeps) in zip(ids, work):
+                tickets.append(srv.submit(mid, *sweeps[s]))
+        for t in tickets:
+            assert srv.wait(t)[0] == 0
+        got = [srv.read(mid, A.shape[0], A.shape[1]) for mid, (A, _) in zip(ids, work)]
+        st = srv.stats()
+        assert st["sweeps_done"] == 20 * len(reqs) and st["sweeps_failed"] == 0
+        assert st["mean_batch"] > 1.0
+    assert rs.device_status(reset=True) == 0
+    rng = np.random.default_rng(7)
+    for (A, sweeps), g, r in zip(work, got, reqs):
+        m = A.shape[0]
+        rows = np.unique(np.concatenate([[0, 63, 64, m - 1], rng.choice(m, 12, replace=False)]))
+        ref = oracle_sweeps(A[rows], sweeps)
+        err = relerr(g[rows], ref, A[rows])
+        drift = np.max(np.abs(np.linalg.norm(g, axis=1) / np.linalg.norm(A, axis=1) - 1.0))
+        say(f"  n={r['n']} k={r['k']}: rel err {err:.3e}, row-norm drift {drift:.1e}")
+        assert err <= 4 * TOL["f64"], (r["n"], r["k"])
+        assert drift <= 1e-12
