@@ -52,6 +52,8 @@ extern "C" {
 #define ROTSEQ_E_INVAL        7  /* unknown matrix id or ticket                 */
 #define ROTSEQ_E_CLOSED       8  /* the matrix was closed                       */
 #define ROTSEQ_E_FAILED       9  /* an earlier sweep of this matrix failed      */
+#define ROTSEQ_E_TOO_LARGE   10  /* the problem's workspace exceeds the fixed
+                                      scratch of rotseq_noalloc_d               */
 
 /* Bit of the device status word (rotseq_device_status) set by the
  * preparation kernels of rotseq_refl_ex_{d,s} when a reflector with tau != 0
@@ -151,6 +153,27 @@ int rotseq_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
 int rotseq_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
              const float *C, int64_t ldc, const float *S, int64_t lds,
              hipStream_t stream);
+
+/*
+ * rotseq_noalloc_d: rotseq_d for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, semantics, layouts and return codes as
+ * rotseq_d, same kernels and launch shape (bitwise the same result), but
+ * the call allocates nothing: its workspace lives in a fixed 64 MiB array
+ * in device memory that the library holds on each device it runs on until
+ * the process ends (the first 256 bytes hold this entry point's error
+ * word, reported by rotseq_device_status).  A problem whose workspace
+ * (rotseq_workspace_bytes('d', m, n, k, NULL)) exceeds 64 MiB - 256 bytes
+ * returns ROTSEQ_E_TOO_LARGE before anything is launched; m = n = 10240
+ * with k = 192 needs 34 MB.  The first call on a device looks up the
+ * array's device address and clears its error word with a kernel on
+ * `stream`.  Every call on a device uses that device's one array, so calls
+ * that overlap on one device (on different streams, or from several host
+ * threads) race and give wrong results: order them on one stream.
+ */
+int rotseq_noalloc_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
+                     const double *C, int64_t ldc, const double *S, int64_t lds,
+                     hipStream_t stream);
 
 /*
  * rotseq_ex_d / rotseq_ex_s: as rotseq_d / rotseq_s with
@@ -278,7 +301,8 @@ int rotseq_profile_read(rotseq_profile *out, int reset);
  * its low byte is ROTSEQ_E_TIMEOUT once a bounded wait between workgroups
  * has given up (the results of that call are then invalid; bits 8-15 say
  * which kind of wait), and ROTSEQ_STATUS_NOT_ORTHOGONAL is set when a
- * reflector call was given a reflector that is not orthogonal.  Batch
+ * reflector call was given a reflector that is not orthogonal.  The word of
+ * rotseq_noalloc_d (in its fixed array) is ORed in and reset with it.  Batch
  * plans and the server keep their own words (rotseq_batch_status, ticket
  * statuses).  This call synchronizes the device, returns the word and, if
  * `reset` is nonzero, clears it.

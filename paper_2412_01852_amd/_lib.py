@@ -117,7 +117,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     i64, vp, i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
     base = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]
-    for name in ("rotseq_d", "rotseq_s"):
+    for name in ("rotseq_d", "rotseq_s", "rotseq_noalloc_d"):
         f = getattr(lib, name)
         f.restype, f.argtypes = i32, base
     for name in ("rotseq_ex_d", "rotseq_ex_s", "rotseq_refl_ex_d", "rotseq_refl_ex_s"):
@@ -241,6 +241,28 @@ def rotseq(A, C, S, *, opts=None, workspace=None, stream=None):
     one).  Returns A.
     """
     return _call(False, A, C, S, opts, workspace, stream)
+
+
+def rotseq_noalloc(A, C, S, *, stream=None):
+    """rotseq_noalloc_d: as rotseq for float64 tensors, with the workspace in
+    the library's fixed device array (nothing is allocated).  Returns A."""
+    import torch
+    if A.dtype != torch.float64 or C.dtype != A.dtype or S.dtype != A.dtype:
+        raise TypeError("rotseq_noalloc takes float64 A, C and S")
+    m, n = A.shape
+    k = C.shape[1]
+    if C.shape != S.shape or C.shape[0] != max(n - 1, 0):
+        raise ValueError(f"coefficient arrays must be ({max(n - 1, 0)}, k); got {tuple(C.shape)}, {tuple(S.shape)}")
+    for t, nm in ((A, "A"), (C, "C"), (S, "S")):
+        if t.numel() and not t.is_cuda:
+            raise ValueError(f"{nm} must be a device tensor")
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    rc = _load().rotseq_noalloc_d(m, n, k, ptr(A), _ld(A, "A"), ptr(C), _ld(C, "C"), ptr(S),
+                                  _ld(S, "S"), ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RotseqError(rc, "rotseq_noalloc")
+    return A
 
 
 def reflseq(A, TAU, NU, *, opts=None, workspace=None, stream=None):

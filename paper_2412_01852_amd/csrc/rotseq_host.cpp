@@ -672,6 +672,7 @@ const char *rotseq_strerror(int code)
     case ROTSEQ_E_INVAL: return "unknown matrix id or ticket";
     case ROTSEQ_E_CLOSED: return "matrix was closed";
     case ROTSEQ_E_FAILED: return "an earlier sweep of this matrix failed";
+    case ROTSEQ_E_TOO_LARGE: return "workspace exceeds the fixed scratch of rotseq_noalloc_d";
     default: return "unknown error code";
     }
 }
@@ -702,6 +703,10 @@ int rotseq_device_status(int reset)
         return ROTSEQ_E_HIP;
     if (reset && hipMemset(word, 0, sizeof(int)) != hipSuccess)
         return ROTSEQ_E_HIP;
+    int na = 0;
+    if (noalloc_status(reset, &na) != ROTSEQ_SUCCESS)
+        return ROTSEQ_E_HIP;
+    v |= na;
     if (reset && hipDeviceSynchronize() != hipSuccess)
         return ROTSEQ_E_HIP;
     return v;

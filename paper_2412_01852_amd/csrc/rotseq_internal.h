@@ -120,6 +120,10 @@ bool make_plan(Plan &p, int req_kernel, int req_band);
 int wait_spin_limit();
 int wait_bias();
 
+// Error word of rotseq_noalloc_d on the current device (0 if it never ran
+// there); `reset` clears it.  Host-only, synchronous.
+int noalloc_status(int reset, int *value);
+
 // Fills the launch shape of `p` for the current device (queries its CU count
 // and occupancy).  `req_waves` > 0 forces the waves per workgroup.
 hipError_t configure_launch(Plan &p, int req_waves, int req_publish);

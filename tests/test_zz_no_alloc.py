@@ -1,0 +1,99 @@
+"""rotseq_noalloc_d (the plain FP64 call with its workspace in the library's
+fixed device array) through the C ABI, against rotseq_d on the same inputs:
+two calls in a row, the second on a smaller problem, each bitwise equal to
+rotseq_d (same kernels and launch shape) and within 1e-13 of the oracle;
+free device memory unchanged by the calls; a problem too large for the
+array refused before anything is launched."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2412_01852_amd as rs
+from paper_2412_01852_amd.inputs import make_problem
+from gpu_util import TOL, relerr, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+E_TOO_LARGE = 10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def _abi_call(fn, A, C, S, stream):
+    m, n = A.shape
+    return fn(m, n, C.shape[1], A.data_ptr(), A.stride(1), C.data_ptr(), C.stride(1),
+              S.data_ptr(), S.stride(1), ctypes.c_void_p(stream.cuda_stream))
+
+
+def test_noalloc_matches_rotseq_d_twice_then_smaller():
+    import torch
+    lib = ctypes.CDLL(rs.library_path())
+    for name in ("rotseq_d", "rotseq_noalloc_d"):
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p, ctypes.c_int64] * 3 + [
+            ctypes.c_void_p]
+    stream = torch.cuda.Stream()
+    # a large call (many tiles, 24 bands over workgroups), then a small one
+    # with ragged tiles, padded leading dimensions and k not a multiple of 8
+    shapes = [(3000, 2500, 192, 0, 0, 0, 7), (130, 301, 45, 3, 2, 1, 8)]
+    free_before = None
+    for i, (m, n, k, pa, pc, ps, seed) in enumerate(shapes):
+        say(f"noalloc call {i}: m={m} n={n} k={k}")
+        pb = make_problem(m, n, k, seed=seed, lda=m + pa, ldc=n - 1 + pc, lds=n - 1 + ps)
+        A1, A2 = to_dev(pb.A, "f64"), to_dev(pb.A, "f64")
+        C, S = to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+        torch.cuda.synchronize()
+        if free_before is None:
+            # The first calls load the code objects and set up the stream's
+            # hardware queue inside the HIP runtime; the calls' own memory
+            # use is measured from then on.
+            A0 = to_dev(pb.A, "f64")
+            free = [torch.cuda.mem_get_info()[0]]
+            for _ in range(3):
+                assert _abi_call(lib.rotseq_noalloc_d, A0, C, S, stream) == 0
+                torch.cuda.synchronize()
+                free.append(torch.cuda.mem_get_info()[0])
+            say(f"  free device memory around the warm-up calls: {free}")
+            free_before = free[-1]
+            del A0
+        torch.cuda.synchronize()
+        f0 = torch.cuda.mem_get_info()[0]
+        assert _abi_call(lib.rotseq_noalloc_d, A1, C, S, stream) == 0
+        torch.cuda.synchronize()
+        f1 = torch.cuda.mem_get_info()[0]
+        say(f"  free device memory before and after the call: {f0} {f1}")
+        assert f1 == f0, "the no-alloc call allocated device memory"
+        assert _abi_call(lib.rotseq_d, A2, C, S, stream) == 0
+        torch.cuda.synchronize()
+        assert rs.device_status(reset=True) == 0
+        assert torch.equal(A1, A2), f"call {i}: differs from rotseq_d"
+        ref = oracle.colmajor(np.asarray(pb.A))
+        oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
+        assert relerr(rs.host_colmajor(A1), np.asarray(ref), pb.A) <= TOL["f64"]
+
+
+def test_noalloc_refuses_problems_beyond_the_array():
+    """m = 64, n = 10240 with k = 768 needs about 136 MB of workspace:
+    refused with ROTSEQ_E_TOO_LARGE before any launch, A unchanged."""
+    import torch
+    m, n, k = 64, 10240, 768
+    assert rs.workspace_bytes("d", m, n, k) > (64 << 20)
+    A = torch.ones((n, m), dtype=torch.float64, device="cuda").t()
+    C = torch.ones((k, n - 1), dtype=torch.float64, device="cuda").t()
+    S = torch.zeros((k, n - 1), dtype=torch.float64, device="cuda").t()
+    with pytest.raises(rs.RotseqError) as e:
+        rs.rotseq_noalloc(A, C, S)
+    assert e.value.code == E_TOO_LARGE
+    torch.cuda.synchronize()
+    assert bool(torch.all(A == 1.0))
+    # the 10240^2, k = 192 problem fits
+    assert rs.workspace_bytes("d", 10240, 10240, 192) <= (64 << 20) - 256
