@@ -438,6 +438,37 @@ def trace_summary(path, last):
     return 0
 
 
+def bench_ceiling(args):
+    """FP64 issue ceilings of the device (rotseq_fp64_ceiling): vector FMAs
+    with register operands, with a DPP-broadcast operand (the sweep's form),
+    matrix FMAs (v_mfma_f64_16x16x4f64, 8 independent accumulators per
+    wave) and both at once, each after a warm-up long enough for the clock
+    to settle, with the average shader clock of the timed run."""
+    import paper_2412_01852_amd as rs
+    runs = []
+    for mode, waves in ((1, 16), (2, 16), (2, 8), (3, 16), (3, 8), (3, 4), (4, 16), (5, 16), (5, 8)):
+        probe = rs.fp64_ceiling(mode, waves, 4096)
+        per_iter_ms = probe["ms"] / 4096
+        iters = max(4, int(0.06 / max(per_iter_ms * 1e-3, 1e-12)) // 4 * 4)  # about 60 ms
+        for _ in range(5):  # about 300 ms of warm-up at this load
+            rs.fp64_ceiling(mode, waves, iters)
+        r = rs.fp64_ceiling(mode, waves, iters)
+        tf_v = r["valu_flops"] / (r["ms"] * 1e-3) / 1e12
+        tf_m = r["mfma_flops"] / (r["ms"] * 1e-3) / 1e12
+        peak_at_clock = PEAK_TFLOPS["f64"] * r["clock_mhz"] / 2400.0
+        runs.append({"mode": {1: "valu", 2: "valu_dpp", 3: "mfma", 4: "valu_dpp+mfma",
+                              5: "mfma+lds"}[mode],
+                     "waves_per_cu": waves, "iters": iters, "ms": round(r["ms"], 3),
+                     "valu_tflops": round(tf_v, 2), "mfma_tflops": round(tf_m, 2),
+                     "total_tflops": round(tf_v + tf_m, 2), "clock_mhz": round(r["clock_mhz"], 1),
+                     "frac_of_peak_at_clock": round((tf_v + tf_m) / peak_at_clock, 4)})
+        print(f"[ceiling] {runs[-1]}", file=sys.stderr, flush=True)
+    out = {"metric": "FP64 issue ceilings (TFLOP/s)", "workload": "fp64-ceiling", "n_gpus": 1,
+           "peak_tflops_f64": PEAK_TFLOPS["f64"], "peak_clock_mhz": 2400, "runs": runs}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,7 +477,7 @@ def main():
     # sustained load; the untimed warm-up covers that.
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default=DEFAULT,
-                    choices=sorted(WORKLOADS) + sorted(BATCHED) + sorted(SERVED))
+                    choices=sorted(WORKLOADS) + sorted(BATCHED) + sorted(SERVED) + ["fp64-ceiling"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), the "
                          "reference for scaling HBM byte counters")
@@ -478,6 +509,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
         return 0
+    if args.workload == "fp64-ceiling":
+        return bench_ceiling(args)
     if args.workload in BATCHED:
         return bench_batched(args)
     if args.workload in SERVED:

@@ -525,6 +525,35 @@ int rotseq_server_stats_get(rotseq_server *srv, rotseq_server_stats *stats);
 /* Runs everything queued, stops the worker and frees all device memory. */
 int rotseq_server_destroy(rotseq_server *srv);
 
+/*
+ * Measured FP64 ceilings of the current device (a synchronous diagnostic).
+ * Launches one workgroup of `waves` waves (1..16) per CU; every wave runs 8
+ * independent dependency chains for `iters` iterations (a positive multiple
+ * of 4) of
+ *   mode 1: v_fmac_f64 with register operands,
+ *   mode 2: v_fmac_f64 with one operand broadcast by DPP row_newbcast (the
+ *           form of the rotation sweep's coefficients),
+ *   mode 3: v_mfma_f64_16x16x4f64 (2048 flops each),
+ *   mode 4: half the waves mode 2, half mode 3, both kinds on every SIMD
+ *           (`waves` a multiple of 8), which shows whether the vector and
+ *           matrix units overlap,
+ *   mode 5: mode 3 with, after every 8 matrix instructions, 8 doubles per
+ *           lane written to LDS and read back into the next B operands (the
+ *           LDS traffic of a sweep built on matrix instructions).
+ * Fills `out` with the kernel time (HIP events), the FP64 flops done by each
+ * kind of instruction and the average shader clock over the run (shader
+ * cycle counter against the 100 MHz real-time counter).  Returns 0, -i for
+ * a bad argument i, or ROTSEQ_E_NOMEM / ROTSEQ_E_HIP.  Allocates and frees
+ * small device buffers; blocks until done.
+ */
+typedef struct rotseq_ceiling_result {
+    double ms;          /* kernel duration                                  */
+    double valu_flops;  /* FP64 flops of the vector FMAs                    */
+    double mfma_flops;  /* FP64 flops of the matrix instructions            */
+    double clock_mhz;   /* average shader clock during the kernel           */
+} rotseq_ceiling_result;
+int rotseq_fp64_ceiling(int32_t mode, int32_t waves, int64_t iters, rotseq_ceiling_result *out);
+
 /* Static description of a return code. */
 const char *rotseq_strerror(int code);
 

@@ -10,6 +10,6 @@ from ._lib import (  # noqa: F401
     KERNEL_AUTO, KERNEL_MULTIPASS, KERNEL_CHAIN,
     rotseq, rotseq_noalloc, reflseq, refl3seq, refl3_workspace_bytes, check_args, workspace_bytes, strerror, version, library_path,
     device_colmajor, host_colmajor, profile_enable, profile_read, device_status,
-    STATUS_NOT_ORTHOGONAL, test_set_waits,
+    STATUS_NOT_ORTHOGONAL, test_set_waits, fp64_ceiling,
     Problem, BatchInfo, Batch, batched, Server, ServerConfig, ServerStats, SweepInfo,
 )

@@ -63,6 +63,22 @@ class SweepInfo(ctypes.Structure):
                 ("end_us", ctypes.c_double)]
 
 
+class CeilingResult(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("valu_flops", ctypes.c_double),
+                ("mfma_flops", ctypes.c_double), ("clock_mhz", ctypes.c_double)]
+
+
+def fp64_ceiling(mode, waves=16, iters=1 << 16):
+    """rotseq_fp64_ceiling: FP64 issue rates of the device (mode 1 vector FMA,
+    2 vector FMA with a DPP-broadcast operand, 3 matrix FMA, 4 both at once);
+    returns a dict with ms, valu_flops, mfma_flops, clock_mhz."""
+    out = CeilingResult()
+    rc = _load().rotseq_fp64_ceiling(int(mode), int(waves), int(iters), ctypes.byref(out))
+    if rc != 0:
+        raise RotseqError(rc, "fp64_ceiling")
+    return {f: getattr(out, f) for f, _ in CeilingResult._fields_}
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("sweeps_done", ctypes.c_int64), ("sweeps_failed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("matrices_resident", ctypes.c_int64),
@@ -139,6 +155,8 @@ def _load():
     lib.rotseq_version.argtypes = []
     lib.rotseq_device_status.restype = i32
     lib.rotseq_device_status.argtypes = [i32]
+    lib.rotseq_fp64_ceiling.restype = i32
+    lib.rotseq_fp64_ceiling.argtypes = [ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(CeilingResult)]
     lib.rotseq_test_set_waits.restype = i32
     lib.rotseq_test_set_waits.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.rotseq_profile_enable.restype = i32
