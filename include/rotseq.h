@@ -84,6 +84,16 @@ extern "C" {
  * each other through LDS inside a workgroup and through A (with device-scope
  * progress counters) across workgroups; one workgroup per CU.  Default. */
 #define ROTSEQ_KERNEL_CHAIN     2
+/* FP64 matrix instructions (v_mfma_f64_16x16x4f64): every band of 8
+ * sequences is applied 8 wavefront steps at a time as a 16 x 16 window
+ * matrix, accumulated once per call from C and S (the paper's GEMM-based
+ * variant, Section 8); 4/3 of the counted flops are issued, on the matrix
+ * units.  For FP64 right application of rotations in the forward order
+ * (also left application, which runs it on a packed copy) with automatic
+ * arithmetic; ROTSEQ_E_UNSUPPORTED otherwise.  ROTSEQ_KERNEL_AUTO picks it
+ * where its modelled time is lower.  Results agree with the other kernels
+ * up to rounding (not bitwise). */
+#define ROTSEQ_KERNEL_MFMA      3
 
 /*
  * Tuning options; zero-initialise for library defaults.
@@ -117,6 +127,10 @@ extern "C" {
  *           elements, see rotseq_workspace_bytes), sweeps the packed copy
  *           and unpacks it.  Quick return if n == 0, m <= 1 or k == 0.
  *           Not for batches.
+ *   shape   MFMA only: 10 * (bands chained in one wave, 1..3) + (blocks
+ *           of 16 rows per wave), e.g. 35; 0 = auto.  Shapes without a
+ *           compiled kernel return ROTSEQ_E_UNSUPPORTED.  With MFMA,
+ *           `waves` (1..4) is the waves per workgroup.
  */
 typedef struct rotseq_opts {
     int32_t arith;
@@ -126,8 +140,30 @@ typedef struct rotseq_opts {
     int32_t publish;
     int32_t inverse;
     int32_t left;
-    int32_t reserved;
+    int32_t shape;
 } rotseq_opts;
+
+/*
+ * The launch a call with these arguments would make on the current device
+ * (kernel family, band, workgroup shape and workspace), without launching
+ * anything.  Arguments 1-5 and `opts` as for rotseq_ex_d/_s with dtype 'd'
+ * or 's' (pointers are not needed: the shape decides).  Returns 0, -i for
+ * an invalid argument i (1 dtype, 2 m, 3 n, 4 k, 5 lda, 7 out), or
+ * ROTSEQ_E_UNSUPPORTED / ROTSEQ_E_HIP.
+ */
+typedef struct rotseq_launch_info {
+    int32_t kernel;         /* ROTSEQ_KERNEL_* that runs                    */
+    int32_t band;           /* sequences per band                           */
+    int32_t waves;          /* waves per workgroup                          */
+    int32_t workgroups;     /* workgroups of the sweep launch               */
+    int32_t bands_per_wave; /* MFMA: bands chained in one wave              */
+    int32_t rows_per_wave;  /* MFMA: rows of A per wave                     */
+    int32_t segments;       /* MFMA: workgroups along one tile's chain      */
+    int32_t reserved;
+    uint64_t workspace_bytes;
+} rotseq_launch_info;
+int rotseq_launch_describe(char dtype, int64_t m, int64_t n, int64_t k, int64_t lda,
+                           const rotseq_opts *opts, rotseq_launch_info *out);
 
 /*
  * rotseq_d: FP64 rotation sequence, A <- A * prod G(j,p) (Algorithms 1-2).
@@ -159,13 +195,13 @@ int rotseq_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, semantics, layouts and return codes as
  * rotseq_d, same kernels and launch shape (bitwise the same result), but
- * the call allocates nothing: its workspace lives in a fixed 64 MiB array
+ * the call allocates nothing: its workspace lives in a fixed 128 MiB array
  * in device memory that the library holds on each device it runs on until
  * the process ends (the first 256 bytes hold this entry point's error
  * word, reported by rotseq_device_status).  A problem whose workspace
- * (rotseq_workspace_bytes('d', m, n, k, NULL)) exceeds 64 MiB - 256 bytes
+ * (rotseq_workspace_bytes('d', m, n, k, NULL)) exceeds 128 MiB - 256 bytes
  * returns ROTSEQ_E_TOO_LARGE before anything is launched; m = n = 10240
- * with k = 192 needs 34 MB.  The first call on a device looks up the
+ * with k = 192 needs 71 MB.  The first call on a device looks up the
  * array's device address and clears its error word with a kernel on
  * `stream`.  Every call on a device uses that device's one array, so calls
  * that overlap on one device (on different streams, or from several host

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librotseq.so")
 
 ARITH_AUTO, ARITH_EXACT, ARITH_FMA, ARITH_LIFT = 0, 1, 2, 3
-KERNEL_AUTO, KERNEL_MULTIPASS, KERNEL_CHAIN = 0, 1, 2
+KERNEL_AUTO, KERNEL_MULTIPASS, KERNEL_CHAIN, KERNEL_MFMA = 0, 1, 2, 3
 
 _lib = None
 
@@ -28,7 +28,7 @@ class Options(ctypes.Structure):
     _fields_ = [("arith", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("publish", ctypes.c_int32), ("inverse", ctypes.c_int32),
-                ("left", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("left", ctypes.c_int32), ("shape", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -61,6 +61,26 @@ class SweepInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double),
                 ("end_us", ctypes.c_double)]
+
+
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("band", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("bands_per_wave", ctypes.c_int32),
+                ("rows_per_wave", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64)]
+
+
+def launch_describe(dtype, m, n, k, lda=None, opts=None):
+    """rotseq_launch_describe: the launch a call of this shape would make on
+    the current device (dict of rotseq_launch_info)."""
+    ch = {"float64": b"d", "double": b"d", "d": b"d", "float32": b"s", "float": b"s", "s": b"s"}[
+        str(dtype).replace("torch.", "")]
+    out = LaunchInfo()
+    rc = _load().rotseq_launch_describe(ch, m, n, k, lda if lda is not None else max(1, m), _opts(opts),
+                                        ctypes.byref(out))
+    if rc != 0:
+        raise RotseqError(rc, "launch_describe")
+    return {f: getattr(out, f) for f, _ in LaunchInfo._fields_ if f != "reserved"}
 
 
 class CeilingResult(ctypes.Structure):
@@ -155,6 +175,9 @@ def _load():
     lib.rotseq_version.argtypes = []
     lib.rotseq_device_status.restype = i32
     lib.rotseq_device_status.argtypes = [i32]
+    lib.rotseq_launch_describe.restype = i32
+    lib.rotseq_launch_describe.argtypes = [ctypes.c_char, i64, i64, i64, i64, ctypes.POINTER(Options),
+                                           ctypes.POINTER(LaunchInfo)]
     lib.rotseq_fp64_ceiling.restype = i32
     lib.rotseq_fp64_ceiling.argtypes = [ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(CeilingResult)]
     lib.rotseq_test_set_waits.restype = i32

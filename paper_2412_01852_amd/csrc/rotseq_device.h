@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rotseq.h"
 #include "rotseq_internal.h"
 
 namespace rotseq {
@@ -80,6 +81,61 @@ __device__ __forceinline__ void opaque(uint64_t &x) { asm volatile("" : "+s"(x))
 // The lockstep barrier of the chain kernel puts one on each side of its
 // LDS wait and s_barrier, so no LDS access of a group moves past them.
 __device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Keeps a running scalar counter opaque to the optimiser (see opaque()).
+__device__ __forceinline__ void opaque_i(int &x) { asm volatile("" : "+s"(x)); }
+
+// Which wait gave up, recorded in bits 8.. of the status word beside
+// ROTSEQ_E_TIMEOUT: the device-scope flag between workgroups.
+constexpr int kWaitFlag = 1 << 10;
+
+__device__ __forceinline__ void record_timeout(int *status, int kind)
+{
+    __hip_atomic_fetch_or(status, ROTSEQ_E_TIMEOUT | kind, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// End of a lockstep group: this wave's LDS accesses have completed (LGKM
+// count 0; vector memory is not waited for), then all waves of the
+// workgroup meet.  The compiler fences keep LDS accesses on their side.
+__device__ __forceinline__ void group_barrier()
+{
+    compiler_fence();
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0) only
+    __builtin_amdgcn_s_barrier();
+    compiler_fence();
+}
+
+// `groups` lockstep groups without work.
+__device__ __forceinline__ void idle_groups(int groups)
+{
+    for (int i = 0; i < groups; ++i)
+        group_barrier();
+}
+
+// Bounded waits: after a timeout `limit` drops to 0, so the wave never waits
+// again and the grid drains within one time-out per wave; the kind of wait
+// that gave up is collected in `timed_out` and written to the status word
+// once, when the wave ends (a memory write inside the step loop would make
+// the compiler drain every outstanding vector memory operation at each wait
+// site).
+// Waits until the device-scope progress counter exceeds `need` (polls cost
+// a memory round trip, so they get a sixteenth of the LDS budget).
+__device__ __forceinline__ int wait_flag(int *p, int need, int &limit, int &timed_out)
+{
+    int v = uniform(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    for (int polls = 0; v <= need; ++polls) {
+        if (polls >= (limit >> 4)) {
+            timed_out |= kWaitFlag;
+            limit = 0;
+            return 0x7fffffff;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        v = uniform(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    return v;
+}
 
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

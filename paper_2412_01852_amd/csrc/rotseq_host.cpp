@@ -27,14 +27,51 @@ std::atomic<int> g_wait_bias{0};
 int wait_spin_limit() { return g_spin_limit.load(std::memory_order_relaxed); }
 int wait_bias() { return g_wait_bias.load(std::memory_order_relaxed); }
 
-bool make_plan(Plan &p, int req_kernel, int req_band)
+namespace {
+
+// Windows per band of the matrix-instruction sweep: steps 0 .. n+6 in
+// windows of 8 steps.
+int64_t mfma_windows(int64_t n) { return (n + 7 + 7) / 8; }
+
+// Workspace of the matrix-instruction sweep's window matrices, for any
+// bands-per-wave choice (at most 2 padded bands), and of its flags.
+size_t mfma_q_bytes(int64_t n, int64_t k) { return (size_t)((k + 7) / 8 + 2) * (mfma_windows(n) + 1) * 2048; }
+size_t mfma_flag_bytes(int64_t m, int64_t k) { return (size_t)((m + 15) / 16) * ((k + 7) / 8) * sizeof(int); }
+
+}  // namespace
+
+bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok)
 {
     // The chain kernel addresses the n column signs with 32-bit byte
     // offsets; past 2^28 columns the multipass kernel takes over.
     constexpr int64_t kChainMaxN = (int64_t)1 << 28;
+    if (req_kernel == kMfma) {
+        // Window matrices for the forward right application of rotations
+        // to a column-major FP64 matrix with 32-bit column offsets per block.
+        if (!mfma_ok || req_band > 0 && req_band != 8)
+            return false;
+        p.kernel = kMfma;
+        p.band = 8;
+        p.pad = 0;
+        p.unroll = 4;
+        p.npass = (int)((p.k + 7) / 8);
+        p.steps = 0;
+        p.mfma_ok = 1;
+        size_t off = 0;
+        p.off_coef = off;
+        off = align256(off + mfma_q_bytes(p.n, p.k));
+        p.off_negmask = p.off_parity = p.off_sign = off;
+        p.off_flags = off;
+        off = align256(off + mfma_flag_bytes(p.m, p.k));
+        p.total = off;
+        return true;
+    }
     p.kernel = req_kernel == 0 ? (p.n <= kChainMaxN ? kChain : kMultipass) : req_kernel;
     if (p.kernel == kChain && p.n > kChainMaxN)
         return false;
+    // With the automatic choice the launch may still pick the matrix
+    // sweep, so the workspace covers both.
+    p.mfma_ok = req_kernel == 0 && mfma_ok && p.kernel == kChain ? 1 : 0;
     int band = req_band;
     if (p.kernel == kChain) {
         // K = 8 by default.  With 4 < k <= 8 a single band of 8 leaves one
@@ -67,7 +104,10 @@ bool make_plan(Plan &p, int req_kernel, int req_band)
     const int64_t tiles = (p.m + 63) / 64;
     size_t off = 0;
     p.off_coef = off;
-    off = align256(off + (size_t)p.npass * (p.steps + p.pad) * band * 2 * p.esize);
+    size_t coef = (size_t)p.npass * (p.steps + p.pad) * band * 2 * p.esize;
+    if (p.mfma_ok)
+        coef = std::max(coef, mfma_q_bytes(p.n, p.k));
+    off = align256(off + coef);
     p.off_negmask = off;
     off = align256(off + (size_t)p.npass * n1 * sizeof(uint64_t));
     p.off_parity = off;
@@ -75,7 +115,10 @@ bool make_plan(Plan &p, int req_kernel, int req_band)
     p.off_sign = off;
     off = align256(off + (size_t)p.n * p.esize);
     p.off_flags = off;
-    off = align256(off + (size_t)tiles * p.npass * sizeof(int));
+    size_t flags = (size_t)tiles * p.npass * sizeof(int);
+    if (p.mfma_ok)
+        flags = std::max(flags, mfma_flag_bytes(p.m, p.k));
+    off = align256(off + flags);
     p.total = off;
     return true;
 }
@@ -144,8 +187,106 @@ int status_word(int **out)
 
 }  // namespace
 
-hipError_t configure_launch(Plan &p, int req_waves, int req_publish)
+namespace {
+
+// Launch shape of the matrix-instruction sweep with the smallest modelled
+// time; fills the mfma_* fields, waves, nwg, lds_bytes and remap of `p`
+// and returns the modelled time in seconds (or a negative value if no
+// shape fits).  Model: every SIMD issues one 16x16x4 FP64 product every
+// 64 cycles at 2.35 GHz; a workgroup runs its super-steps (barriers
+// included) one after another, each kMfmaEff slower than its products
+// alone (the other instructions of a super-step do not overlap the FP64
+// matrix pipeline; measured at m = n = 10240, k = 192).
+constexpr double kMfmaEff = 0.66;
+
+double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
 {
+    static const int kShapes[][2] = {{3, 5}, {3, 4}, {3, 2}, {2, 4}, {2, 2}, {1, 4}, {1, 2}};
+    const int64_t rb = (p.m + 15) / 16;
+    const int64_t nbands = (p.k + 7) / 8;
+    const int nwin = (int)mfma_windows(p.n);
+    double best = -1.0;
+    Plan keep = p;
+    for (const auto &sh : kShapes) {
+        const int nb = sh[0], rows = sh[1];
+        if (req_shape > 0 && req_shape != 10 * nb + rows)
+            continue;
+        for (int w = 1; w <= 4; ++w) {
+            if (req_waves > 0 && w != req_waves)
+                continue;
+            const int64_t tiles = (rb + rows - 1) / rows;
+            const int64_t nchunks = (nbands + nb - 1) / nb;
+            if (w > nchunks)
+                continue;
+            const int64_t nseg = (nchunks + w - 1) / w;
+            const int64_t nwg = tiles * nseg;
+            if (nwg > INT32_MAX || nchunks * nb > nbands + 2)  // reserved window matrices
+                continue;
+            const size_t lds = mfma_lds_bytes(w, rows);
+            if (lds > d.max_lds)
+                continue;
+            int occ = 0;
+            if (mfma_occupancy(nb, rows, w, lds, &occ) != hipSuccess || occ < 1)
+                continue;
+            const int64_t slots = (int64_t)occ * d.cus;
+            const int64_t rounds = (nwg + slots - 1) / slots;
+            const int64_t resident = std::min<int64_t>(nwg, slots);
+            const int64_t simd_waves = (resident * w + 4 * (int64_t)d.cus - 1) / (4 * (int64_t)d.cus);
+            const int delay = mfma_seg_delay(w, nb);
+            const int64_t T = 4 + (nseg - 1) * delay + (w - 1) * mfma_wave_stride(nb) + 2 * nb - 1 + nwin + 1;
+            const double cycles = (double)rounds * (double)simd_waves * (double)T * nb * rows * 4 * 64;
+            const double t = cycles / 2.35e9 / kMfmaEff;
+            if (best < 0.0 || t < best * 0.999) {
+                best = t;
+                keep = p;
+                keep.mfma_nb = nb;
+                keep.mfma_rows = rows;
+                keep.mfma_nwin = nwin;
+                keep.mfma_nchunks = (int)nchunks;
+                keep.mfma_nseg = (int)nseg;
+                keep.mfma_tiles = (int)tiles;
+                keep.mfma_seg_delay = delay;
+                keep.waves = w;
+                keep.nwg = (int)nwg;
+                keep.lds_bytes = lds;
+                keep.remap = (nwg % 8 == 0 && nwg <= slots) ? 1 : 0;
+            }
+        }
+    }
+    if (best >= 0.0)
+        p = keep;
+    return best;
+}
+
+// Modelled time of the vector chain sweep: its measured rate on large
+// problems (about 44 TFLOP/s counted) with a floor for small ones.
+double model_chain(const Plan &p)
+{
+    const double flops = 6.0 * (double)p.m * (double)(p.n - 1) * (double)p.k;
+    return flops / 44e12 + 20e-6;
+}
+
+}  // namespace
+
+hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_shape)
+{
+    if (p.kernel == kMfma || (p.kernel == kChain && p.mfma_ok)) {
+        DeviceInfo d;
+        if (device_info(d) != ROTSEQ_SUCCESS)
+            return hipErrorInvalidDevice;
+        Plan trial = p;
+        const double t = p.kernel == kMfma ? plan_mfma(trial, req_waves, req_shape, d)
+                                            : plan_mfma(trial, 0, 0, d);
+        if (p.kernel == kMfma && t < 0.0)
+            return hipErrorInvalidConfiguration;
+        if (t >= 0.0 && (p.kernel == kMfma || t < model_chain(p))) {
+            p = trial;
+            p.kernel = kMfma;
+            p.spin_limit = wait_spin_limit();
+            p.wait_bias = wait_bias();
+            return hipSuccess;
+        }
+    }
     if (p.kernel != kChain)
         return hipSuccess;
     DeviceInfo d;
@@ -365,9 +506,9 @@ bool resolve(const rotseq_opts *opts, int &arith, int &band, int &kernel)
     if (arith != kExact && arith != kFma && arith != kLift)
         return false;
     if (kernel != ROTSEQ_KERNEL_AUTO && kernel != ROTSEQ_KERNEL_MULTIPASS &&
-        kernel != ROTSEQ_KERNEL_CHAIN)
+        kernel != ROTSEQ_KERNEL_CHAIN && kernel != ROTSEQ_KERNEL_MFMA)
         return false;
-    if (opts && (opts->waves < 0 || opts->waves > 16 || opts->publish < 0))
+    if (opts && (opts->waves < 0 || opts->waves > 16 || opts->publish < 0 || opts->shape < 0))
         return false;
     return true;
 }
@@ -397,7 +538,16 @@ bool plan_for(Plan &p, int esize, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.arith = arith;
     p.kind = kind;
     p.esize = esize;
-    if (!make_plan(p, kernel, band))
+    // The matrix-instruction sweep: forward right application (or the
+    // packed copy of a left application) of rotations, FP64, automatic
+    // arithmetic, with every 8-column block of A within 32-bit offsets.
+    // Automatic choice only when no chain-kernel tuning was asked for.
+    const bool mfma_ok = kind == kRotate && esize == 8 && !(opts && opts->inverse) &&
+                         (opts == nullptr || opts->arith == ROTSEQ_ARITH_AUTO) &&
+                         (kernel == kMfma || opts == nullptr ||
+                          (opts->waves == 0 && opts->publish == 0 && opts->band == 0)) &&
+                         (uint64_t)(left ? p.m : lda) * 8u * 9u < ((uint64_t)1 << 30);
+    if (!make_plan(p, kernel, band, mfma_ok))
         return false;
     off_pack = 0;
     if (left) {
@@ -422,10 +572,11 @@ int run(int kind, int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C
     size_t off_pack = 0;
     if (!plan_for(p, (int)sizeof(T), m, n, k, lda, ldc, lds, opts, kind, off_pack))
         return ROTSEQ_E_UNSUPPORTED;
-    if (p.n > INT32_MAX - 64 || p.steps <= 0)
+    if (p.n > INT32_MAX - 64 || (p.kernel != kMfma && p.steps <= 0))
         return ROTSEQ_E_UNSUPPORTED;
-    if (configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0) != hipSuccess)
-        return ROTSEQ_E_HIP;
+    if (const hipError_t e = configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0,
+                                              opts ? opts->shape : 0))
+        return e == hipErrorInvalidConfiguration ? ROTSEQ_E_UNSUPPORTED : ROTSEQ_E_HIP;
     if (const int rc = status_word(&p.status))
         return rc;
     if (ws) {
@@ -678,6 +829,47 @@ const char *rotseq_strerror(int code)
 }
 
 int rotseq_version(void) { return 100; }
+
+int rotseq_launch_describe(char dtype, int64_t m, int64_t n, int64_t k, int64_t lda,
+                           const rotseq_opts *opts, rotseq_launch_info *out)
+{
+    const int esize = dtype == 'd' ? 8 : dtype == 's' ? 4 : 0;
+    if (!esize)
+        return -1;
+    if (m < 0)
+        return -2;
+    if (n < 0)
+        return -3;
+    if (k < 0)
+        return -4;
+    if (lda < (m > 1 ? m : 1))
+        return -5;
+    if (out == nullptr)
+        return -7;
+    *out = rotseq_launch_info{};
+    const bool left = opts && opts->left;
+    if ((left ? n == 0 || m <= 1 : m == 0 || n <= 1) || k == 0)
+        return ROTSEQ_SUCCESS;
+    Plan p;
+    size_t off_pack = 0;
+    const int64_t n1 = (left ? m : n) - 1;
+    if (!plan_for(p, esize, m, n, k, lda, n1, n1, opts, kRotate, off_pack))
+        return ROTSEQ_E_UNSUPPORTED;
+    if (const hipError_t e = configure_launch(p, opts ? opts->waves : 0, opts ? opts->publish : 0,
+                                              opts ? opts->shape : 0))
+        return e == hipErrorInvalidConfiguration ? ROTSEQ_E_UNSUPPORTED : ROTSEQ_E_HIP;
+    out->kernel = p.kernel;
+    out->band = p.band;
+    out->waves = p.waves;
+    out->workgroups = p.nwg;
+    if (p.kernel == kMfma) {
+        out->bands_per_wave = p.mfma_nb;
+        out->rows_per_wave = 16 * p.mfma_rows;
+        out->segments = p.mfma_nseg;
+    }
+    out->workspace_bytes = p.total;
+    return ROTSEQ_SUCCESS;
+}
 
 int rotseq_test_set_waits(int32_t spin_limit, int32_t unreachable)
 {

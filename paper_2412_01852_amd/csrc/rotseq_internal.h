@@ -19,7 +19,7 @@ enum Arith : int { kExact = 1, kFma = 2, kLift = 3 };
 enum Kind : int { kRotate = 0, kReflect = 1, kReflectRev = 2 };
 
 // Sweep kernel families (values of rotseq_opts.kernel after resolving AUTO).
-enum Kernel : int { kMultipass = 1, kChain = 2 };
+enum Kernel : int { kMultipass = 1, kChain = 2, kMfma = 3 };
 
 // Identity records after the last step of each band for the chain kernel;
 // covers its deepest coefficient look-ahead (16 steps) plus one.
@@ -52,6 +52,12 @@ struct Plan {
     int waves, nwg, remap, publish, spin_limit, wait_bias;
     size_t lds_bytes;
     int *status;  // sticky device error word (ROTSEQ_E_* bits)
+    // Matrix-instruction sweep (kMfma): bands per wave, 16-row blocks per
+    // wave, windows per band, band chunks and workgroups per tile chain,
+    // row tiles, extra super-steps per later segment.  Its window matrices
+    // live at off_coef.
+    int mfma_ok;  // the workspace covers the matrix-instruction sweep
+    int mfma_nb, mfma_rows, mfma_nwin, mfma_nchunks, mfma_nseg, mfma_tiles, mfma_seg_delay;
     // Workspace layout (byte offsets from the workspace base, 256-aligned).
     size_t off_coef, off_negmask, off_parity, off_sign, off_flags, total;
 };
@@ -112,7 +118,10 @@ hipError_t launch_chain_batch(const BatchLaunch &b, hipStream_t stream);
 // Fills the shape-only fields of `p` (kernel, band, npass, steps, unroll,
 // workspace offsets) from its shape and the requested kernel and band
 // (0 = auto).  Returns false for unsupported requests.  Host-only.
-bool make_plan(Plan &p, int req_kernel, int req_band);
+// `mfma_ok`: the problem may run on the matrix-instruction sweep (forward
+// right application of rotations, FP64, automatic arithmetic); with the
+// automatic kernel choice the workspace then covers it as well.
+bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok = false);
 
 // Polls before a wait between workgroups gives up, and the amount added to
 // every such wait's target (0, or past any column count, so that every wait
@@ -126,7 +135,10 @@ int noalloc_status(int reset, int *value);
 
 // Fills the launch shape of `p` for the current device (queries its CU count
 // and occupancy).  `req_waves` > 0 forces the waves per workgroup.
-hipError_t configure_launch(Plan &p, int req_waves, int req_publish);
+// `req_shape` > 0 forces the matrix sweep's (bands, row blocks) per wave as
+// 10 * bands + blocks.  hipErrorInvalidConfiguration: a forced matrix sweep
+// has no shape that fits.
+hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_shape = 0);
 
 // Register-ring length (= unroll length) of the sweep kernels for a band.
 int unroll_for_band(int band);
@@ -136,8 +148,19 @@ hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds
                            bool batch = false);
 hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stream);
 
+// Matrix-instruction sweep (rotseq_mfma.hip).
+bool mfma_shape_supported(int nb_wave, int rows);
+int mfma_wave_stride(int nb_wave);
+int mfma_seg_delay(int waves, int nb_wave);
+size_t mfma_lds_bytes(int waves, int rows);
+hipError_t mfma_occupancy(int nb_wave, int rows, int waves, size_t lds, int *blocks);
+hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t stream);
+hipError_t launch_mfma(const Plan &p, void *A, const void *ws, hipStream_t stream);
+
 // Launchers (rotseq_kernels.hip).  All are asynchronous on `stream` and
 // return the hipError_t of the launch.
+// p[0 .. count) = 0 by a kernel (also under graph capture).
+hipError_t launch_zero(int *p, int64_t count, hipStream_t stream);
 hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws,
                        hipStream_t stream);
 hipError_t launch_sweep(const Plan &p, void *A, const void *ws, hipStream_t stream);

@@ -558,8 +558,18 @@ hipError_t sweep_t(const Plan &p, T *A, const char *ws, hipStream_t st)
 
 int unroll_for_band(int band) { return band + 1 + kPrefetch; }
 
+hipError_t launch_zero(int *p, int64_t count, hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    prep_zero<<<blocks_for(count, 256), 256, 0, stream>>>(p, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t stream)
 {
+    if (p.kernel == kMfma)
+        return launch_mfma_prep(p, C, S, ws, stream);
     if (p.esize == 8)
         return prep_t<double>(p, (const double *)C, (const double *)S, (char *)ws, stream);
     return prep_t<float>(p, (const float *)C, (const float *)S, (char *)ws, stream);
@@ -595,6 +605,8 @@ hipError_t launch_sweep(const Plan &p, void *A, const void *ws, hipStream_t stre
 {
     if (p.kernel == kChain)
         return launch_chain(p, A, ws, stream);
+    if (p.kernel == kMfma)
+        return launch_mfma(p, A, ws, stream);
     if (p.esize == 8)
         return sweep_t<double>(p, (double *)A, (const char *)ws, stream);
     return sweep_t<float>(p, (float *)A, (const char *)ws, stream);

@@ -20,10 +20,11 @@
 
 namespace rotseq {
 
-// Status word, then one call's workspace; 64 MiB covers m = n = 10240 with
-// k up to about 360 (k = 192 needs 34 MB).
+// Status word, then one call's workspace; 128 MiB covers m = n = 10240
+// with k up to about 360 (k = 192 needs 71 MB with the window matrices of
+// the matrix-instruction sweep).
 constexpr size_t kScratchHead = 256;
-constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr size_t kScratchBytes = (size_t)128 << 20;
 
 namespace {
 
@@ -111,7 +112,10 @@ extern "C" int rotseq_noalloc_d(int64_t m, int64_t n, int64_t k, double *A, int6
     p.arith = kLift;
     p.kind = kRotate;
     p.esize = (int)sizeof(double);
-    if (!make_plan(p, 0, 0) || p.n > INT32_MAX - 64 || p.steps <= 0)
+    // The same plan as rotseq_d: forward right application of rotations in
+    // FP64 with automatic arithmetic, so the matrix sweep is eligible.
+    const bool mfma_ok = (uint64_t)lda * 8u * 9u < ((uint64_t)1 << 30);
+    if (!make_plan(p, 0, 0, mfma_ok) || p.n > INT32_MAX - 64 || (p.kernel != kMfma && p.steps <= 0))
         return ROTSEQ_E_UNSUPPORTED;
     if (p.total > kScratchBytes - kScratchHead)
         return ROTSEQ_E_TOO_LARGE;

@@ -178,7 +178,7 @@ def test_new_error_codes_have_descriptions():
 
 def test_options_struct_layout():
     """rotseq_opts is eight int32 fields: arith, kernel, band, waves, publish,
-    inverse, left, reserved."""
+    inverse, left, shape."""
     assert ctypes.sizeof(rs.Options) == 32
     assert rs.Options.inverse.offset == 20
     assert rs.Options.left.offset == 24

@@ -61,7 +61,7 @@ def test_plain_call_reports_timeout(unreachable_waits):
     say("errors: plain call, forced wait time-out")
     import torch
     A, C, S = _dev(make_problem(130, 300, 64, seed=401))
-    rs.rotseq(A, C, S, opts={"waves": 4})
+    rs.rotseq(A, C, S, opts={"waves": 4, "kernel": rs.KERNEL_CHAIN})
     torch.cuda.synchronize()
     st = rs.device_status(reset=True)
     assert st & 0xff == E_TIMEOUT, hex(st)
@@ -74,7 +74,7 @@ def test_plain_call_single_workgroup_chain_stays_clean(unreachable_waits):
     import torch
     pb = make_problem(130, 300, 64, seed=402)
     A, C, S = _dev(pb)
-    rs.rotseq(A, C, S, opts={"waves": 8})
+    rs.rotseq(A, C, S, opts={"waves": 8, "kernel": rs.KERNEL_CHAIN})
     torch.cuda.synchronize()
     assert rs.device_status(reset=True) == 0
     ref = oracle.colmajor(np.asarray(pb.A))

@@ -1,0 +1,178 @@
+"""GPU parity of the matrix-instruction sweep (ROTSEQ_KERNEL_MFMA) through
+the C ABI against the CPU oracle.
+
+The sweep applies every band of 8 sequences as 16 x 16 window matrices on
+v_mfma_f64_16x16x4f64; results agree with Algorithm 2 up to rounding, so
+the bar is the FP64 tolerance, 1e-13 relative Frobenius error.  Shapes
+cover one row tile and many, ragged row tiles (m not a multiple of 16),
+n below one window, k below, at and above a band, padded leading
+dimensions, every compiled wave shape, one to four waves per workgroup (so
+chains crossing workgroups through A and flags), padded bands, left
+application on the packed copy, the automatic choice at the full target
+size, the error path of a wait that gives up, and refused combinations.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2412_01852_amd as rs
+from paper_2412_01852_amd.inputs import make_left_problem, make_problem
+from gpu_util import TOL, padding_bits, relerr, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MFMA = rs.KERNEL_MFMA
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+def run_mfma(pb, opts):
+    """Returns (gpu result, oracle result, padding untouched)."""
+    import torch
+    A, C, S = to_dev(pb.A, "f64"), to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    pad_before = padding_bits(A)
+    rs.rotseq(A, C, S, opts=opts)
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0, "a device-side wait timed out"
+    ref = oracle.colmajor(np.asarray(pb.A))
+    oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
+    return rs.host_colmajor(A), np.asarray(ref), np.array_equal(pad_before, padding_bits(A))
+
+
+EDGE = [
+    # m, n, k, lda pad, ldc pad, lds pad
+    (1, 2, 1, 0, 0, 0), (15, 3, 2, 1, 0, 2), (16, 9, 7, 0, 0, 0), (17, 16, 8, 3, 1, 0),
+    (64, 64, 64, 0, 0, 0), (130, 17, 33, 2, 3, 1), (100, 5, 20, 0, 0, 0), (70, 40, 17, 6, 0, 0),
+    (1, 300, 3, 0, 0, 0), (81, 200, 9, 0, 0, 0), (200, 2, 1, 0, 0, 0), (3, 129, 128, 1, 1, 1),
+    (333, 211, 59, 7, 0, 0), (48, 25, 24, 0, 2, 2),
+]
+
+
+@pytest.mark.parametrize("m,n,k,pa,pc,ps", EDGE)
+def test_mfma_edges(m, n, k, pa, pc, ps):
+    say(f"mfma edge m={m} n={n} k={k} pads={pa},{pc},{ps}")
+    pb = make_problem(m, n, k, seed=11 * m + 3 * n + k,
+                      lda=max(1, m) + pa, ldc=max(1, n - 1) + pc, lds=max(1, n - 1) + ps)
+    got, ref, pad_ok = run_mfma(pb, {"kernel": MFMA})
+    assert pad_ok, "padding rows of A were modified"
+    assert relerr(got, ref, pb.A) <= TOL["f64"]
+
+
+SHAPES = [35, 34, 32, 24, 22, 14, 12]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("waves", [1, 2, 3, 4])
+def test_mfma_shapes_and_workgroups(shape, waves):
+    """Every compiled (bands, row blocks) per wave with 1-4 waves per
+    workgroup: 11 bands (padded to the chunk size), 13 row blocks with a
+    ragged last one, so tiles are partial and chains cross workgroups."""
+    say(f"mfma shape={shape} waves={waves}")
+    pb = make_problem(200, 301, 83, seed=shape * 10 + waves, lda=203)
+    info = rs.launch_describe("d", 200, 301, 83, lda=203, opts={"kernel": MFMA, "shape": shape,
+                                                              "waves": waves})
+    assert info["kernel"] == MFMA and info["waves"] == waves
+    assert info["bands_per_wave"] == shape // 10 and info["rows_per_wave"] == 16 * (shape % 10)
+    got, ref, pad_ok = run_mfma(pb, {"kernel": MFMA, "shape": shape, "waves": waves})
+    assert pad_ok
+    assert relerr(got, ref, pb.A) <= TOL["f64"]
+
+
+def test_mfma_left_application():
+    """Rows mixed (left application) through the packed copy on the matrix sweep."""
+    import torch
+    say("mfma left application")
+    pb = make_left_problem(300, 90, 40, seed=21, lda=305)
+    A, C, S = to_dev(pb.A, "f64"), to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    pad_before = padding_bits(A)
+    rs.rotseq(A, C, S, opts={"kernel": MFMA, "left": 1})
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
+    ref = oracle.colmajor(np.asarray(pb.A))
+    oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S), left=True)
+    assert np.array_equal(pad_before, padding_bits(A))
+    assert relerr(rs.host_colmajor(A), np.asarray(ref), pb.A) <= TOL["f64"]
+
+
+def test_mfma_repeated_calls_compose():
+    """Two calls compose (A Q Q), and the pooled workspace serves both."""
+    import torch
+    say("mfma repeated calls")
+    pb = make_problem(160, 500, 48, seed=31)
+    A, C, S = to_dev(pb.A, "f64"), to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    rs.rotseq(A, C, S, opts={"kernel": MFMA})
+    rs.rotseq(A, C, S, opts={"kernel": MFMA})
+    torch.cuda.synchronize()
+    ref = oracle.colmajor(np.asarray(pb.A))
+    for _ in range(2):
+        oracle.rotseq(ref, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
+    assert relerr(rs.host_colmajor(A), np.asarray(ref), pb.A) <= 2 * TOL["f64"]
+
+
+def test_auto_choice_at_the_target_size():
+    """The automatic choice at m = n = 10240, k = 192 (the bench's launch)
+    is one of the two sweeps; whichever it is, test_target_10240_k192_full
+    checks it on every element, and the matrix sweep forced at that size is
+    checked below."""
+    info = rs.launch_describe("d", 10240, 10240, 192)
+    say(f"target launch: {info}")
+    assert info["kernel"] in (rs.KERNEL_CHAIN, MFMA)
+
+
+def test_mfma_forced_at_the_target_size_sampled_rows():
+    """m = n = 10240, k = 192 on the matrix sweep (256 workgroups, chains
+    crossing workgroups): sampled rows against the oracle, every row's norm
+    preserved."""
+    from test_gpu_parity import run_sampled
+    say("target 10240x10240 k=192 f64 kernel=mfma (sampled rows)")
+    err, drift = run_sampled(10240, 10240, 192, 2, "f64", {"kernel": MFMA})
+    say(f"  rel err {err:.3e}  max row-norm drift {drift:.3e}")
+    assert err <= TOL["f64"]
+    assert drift <= 1e-12
+
+
+@pytest.mark.parametrize("opts,dtype", [({"kernel": MFMA}, "f32"),
+                                        ({"kernel": MFMA, "inverse": 1}, "f64"),
+                                        ({"kernel": MFMA, "arith": rs.ARITH_EXACT}, "f64"),
+                                        ({"kernel": MFMA, "band": 4}, "f64"),
+                                        ({"kernel": MFMA, "shape": 99}, "f64")])
+def test_mfma_refuses_unsupported(opts, dtype):
+    import torch
+    pb = make_problem(20, 30, 5, seed=1)
+    A = to_dev(pb.A, dtype)
+    with pytest.raises(rs.RotseqError) as e:
+        rs.rotseq(A, to_dev(pb.C, dtype), to_dev(pb.S, dtype), opts=opts)
+    assert e.value.code == 4  # ROTSEQ_E_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert np.array_equal(rs.host_colmajor(A), np.asarray(pb.A, dtype=np.float32 if dtype == "f32"
+                                                          else np.float64).astype(np.float64))
+
+
+def test_mfma_wait_timeout_reported():
+    """One wave per workgroup puts every band chunk in its own workgroup;
+    with unreachable waits every later chunk gives up and the status word
+    says so; the kernels still complete."""
+    import torch
+    say("mfma forced wait time-out")
+    pb = make_problem(100, 120, 48, seed=41)
+    A, C, S = to_dev(pb.A, "f64"), to_dev(pb.C, "f64"), to_dev(pb.S, "f64")
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
+    rs.test_set_waits(1, unreachable=True)
+    try:
+        rs.rotseq(A, C, S, opts={"kernel": MFMA, "shape": 12, "waves": 1})
+        torch.cuda.synchronize()
+        st = rs.device_status(reset=True)
+    finally:
+        rs.test_set_waits(0, unreachable=False)
+    assert st & 0xff == 5, hex(st)
+    rs.rotseq(A, C, S, opts={"kernel": MFMA, "shape": 12, "waves": 1})
+    torch.cuda.synchronize()
+    assert rs.device_status(reset=True) == 0
