@@ -31,12 +31,19 @@ namespace {
 
 // Windows per band of the matrix-instruction sweep: steps 0 .. n+6 in
 // windows of 8 steps.
-int64_t mfma_windows(int64_t n) { return (n + 7 + 7) / 8; }
+int64_t mfma_windows(int64_t n) { return (n + 7) / 8; }
 
 // Workspace of the matrix-instruction sweep's window matrices, for any
 // bands-per-wave choice (at most 2 padded bands), and of its flags.
 size_t mfma_q_bytes(int64_t n, int64_t k) { return (size_t)((k + 7) / 8 + 2) * (mfma_windows(n) + 1) * 2048; }
-size_t mfma_flag_bytes(int64_t m, int64_t k) { return (size_t)((m + 15) / 16) * ((k + 7) / 8) * sizeof(int); }
+// One progress flag per (tile, segment), each on its own 128-byte line
+// (polled by one workgroup while another writes it through every
+// super-step; neighbours on one line would share that traffic).  Tiles are
+// at least 2 row blocks and segments at least 4 bands.
+size_t mfma_flag_bytes(int64_t m, int64_t k)
+{
+    return (size_t)(((m + 15) / 16 + 1) / 2) * (size_t)(((k + 7) / 8 + 3) / 4) * (size_t)kMfmaFlagStride * sizeof(int);
+}
 
 }  // namespace
 
@@ -197,7 +204,7 @@ namespace {
 // included) one after another, each kMfmaEff slower than its products
 // alone (the other instructions of a super-step do not overlap the FP64
 // matrix pipeline; measured at m = n = 10240, k = 192).
-constexpr double kMfmaEff = 0.66;
+constexpr double kMfmaEff = 0.75;
 
 double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
 {
@@ -211,29 +218,28 @@ double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
         const int nb = sh[0], rows = sh[1];
         if (req_shape > 0 && req_shape != 10 * nb + rows)
             continue;
-        for (int w = 1; w <= 4; ++w) {
+        {
+            const int w = mfma_waves();
             if (req_waves > 0 && w != req_waves)
                 continue;
             const int64_t tiles = (rb + rows - 1) / rows;
             const int64_t nchunks = (nbands + nb - 1) / nb;
-            if (w > nchunks)
-                continue;
             const int64_t nseg = (nchunks + w - 1) / w;
             const int64_t nwg = tiles * nseg;
             if (nwg > INT32_MAX || nchunks * nb > nbands + 2)  // reserved window matrices
                 continue;
-            const size_t lds = mfma_lds_bytes(w, rows);
+            const size_t lds = mfma_lds_bytes(rows);
             if (lds > d.max_lds)
                 continue;
             int occ = 0;
-            if (mfma_occupancy(nb, rows, w, lds, &occ) != hipSuccess || occ < 1)
+            if (mfma_occupancy(nb, rows, lds, &occ) != hipSuccess || occ < 1)
                 continue;
             const int64_t slots = (int64_t)occ * d.cus;
             const int64_t rounds = (nwg + slots - 1) / slots;
             const int64_t resident = std::min<int64_t>(nwg, slots);
             const int64_t simd_waves = (resident * w + 4 * (int64_t)d.cus - 1) / (4 * (int64_t)d.cus);
-            const int delay = mfma_seg_delay(w, nb);
-            const int64_t T = 4 + (nseg - 1) * delay + (w - 1) * mfma_wave_stride(nb) + 2 * nb - 1 + nwin + 1;
+            const int delay = mfma_seg_delay(nb);
+            const int64_t T = 4 + (nseg - 1) * delay + (w - 1) * mfma_wave_stride(nb) + 2 * nb + nwin;
             const double cycles = (double)rounds * (double)simd_waves * (double)T * nb * rows * 4 * 64;
             const double t = cycles / 2.35e9 / kMfmaEff;
             if (best < 0.0 || t < best * 0.999) {

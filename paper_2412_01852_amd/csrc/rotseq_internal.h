@@ -149,11 +149,13 @@ hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds
 hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stream);
 
 // Matrix-instruction sweep (rotseq_mfma.hip).
+constexpr int kMfmaFlagStride = 32;  // ints between progress flags (128 bytes)
 bool mfma_shape_supported(int nb_wave, int rows);
 int mfma_wave_stride(int nb_wave);
-int mfma_seg_delay(int waves, int nb_wave);
-size_t mfma_lds_bytes(int waves, int rows);
-hipError_t mfma_occupancy(int nb_wave, int rows, int waves, size_t lds, int *blocks);
+int mfma_waves();
+int mfma_seg_delay(int nb_wave);
+size_t mfma_lds_bytes(int rows);
+hipError_t mfma_occupancy(int nb_wave, int rows, size_t lds, int *blocks);
 hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t stream);
 hipError_t launch_mfma(const Plan &p, void *A, const void *ws, hipStream_t stream);
 

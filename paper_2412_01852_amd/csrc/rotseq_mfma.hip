@@ -5,12 +5,14 @@
 //
 // Windows.  Band beta (sequences 8*beta .. 8*beta+7) applies at step t the
 // rotations (t-q, 8*beta+q), q = 0..7 (Section 1.1).  Window w holds steps
-// 8w .. 8w+7, which touch only the 16 columns 8w-7 .. 8w+8; their product
-// is one orthogonal 16 x 16 matrix Q(beta, w), prepared once per call by
-// `mfma_prep_q` (with Q(beta, -1) = I).  With X the 16 window columns of a
-// row tile, the window is X <- X Q.  Afterwards columns 8w-7 .. 8w (block
-// w) are final for the band, and columns 8w+1 .. 8w+8 stay "in flight"
-// into window w+1, whose new columns are block w+1 of the band's input.
+// 8w+7 .. 8w+14, which touch only the 16 columns 8w .. 8w+15; their
+// product is one orthogonal 16 x 16 matrix Q(beta, w), prepared once per
+// call by `mfma_prep_q` for w = -1 .. nwin-1, nwin = ceil(n/8).  With X the
+// 16 window columns of a row tile, the window is X <- X Q.  Afterwards
+// columns 8w .. 8w+7 (block w) are final for the band, and columns 8w+8 ..
+// 8w+15 stay "in flight" into window w+1, whose new columns are block w+1
+// of the band's input.  Blocks never straddle column 0, so a lane's offset
+// within a block is the same for every block.
 // The windows do (16^2 / (3*8*8)) = 4/3 times the counted 6 flops per
 // rotation and row.
 //
@@ -33,13 +35,16 @@
 // two products (StepOps), so the matrix pipeline never waits for an issue.
 //
 // Work decomposition.  A wave owns R row blocks of 16 rows (a tile) and a
-// chunk of NB consecutive bands; the W waves of a workgroup hold W
+// chunk of NB consecutive bands; the 4 waves of a workgroup hold 4
 // consecutive chunks of one tile's chain (a segment); a chain longer than
-// W chunks continues in the next workgroup through A and a progress flag,
-// as in the vector chain kernel.  Super-steps are separated by a workgroup
-// barrier; wave j starts 4*ceil((2NB+3)/4) super-steps after wave j-1 and
-// a later segment `seg_delay` super-steps after the previous one, so every
-// block is produced at least one super-step before it is read (checked by
+// 4 chunks continues in the next workgroup through A and a progress flag,
+// as in the vector chain kernel.  The loads of A (the first wave's input)
+// and the stores (the last wave's output) are shared by all four waves,
+// row block by row block, through an LDS stage and the last wave's ring.
+// Super-steps are separated by a workgroup barrier; wave j starts
+// 4*ceil((2NB+3)/4) super-steps after wave j-1 and a later segment
+// `seg_delay` super-steps after the previous one, so every block is
+// produced at least one super-step before it is read (checked by
 // tests/test_mfma_model.py).  All loop-carried register indices are
 // compile-time: offsets are multiples of the unroll of 4.
 //
@@ -77,15 +82,21 @@ struct MfmaArgs {
     int spin_limit;
     int wait_bias;
     uint64_t q;      // [band][nwin+1][64 lanes][4 slabs] window matrices
-    int *flags;      // [tile][seg] blocks published by the segment's last wave
+    int *flags;      // [tile][seg][32] blocks published by the segment (first int of 128 bytes)
     int *status;
 };
 
-// A wave that hands its blocks to the next workgroup publishes block w one
-// super-step after storing it, once the stores have completed.
-constexpr int kPubLag = 1;
-// Super-steps between a flag store and a poll that is sure to see it.
-constexpr int kFlagMargin = 3;
+// Waves per workgroup (one per SIMD); a workgroup's waves also share the
+// loads and stores of A.
+constexpr int kWaves = 4;
+// Super-steps between a flag poll and the use of its value (the poll of
+// super-step u is read at u of the next trip round the unrolled loop).
+constexpr int kPollLag = kUnroll;
+// Super-steps between storing a block to A and the wait that covers those
+// stores in every wave; the block is published one super-step later.
+constexpr int kPubWait = 2;
+// Super-steps between publishing a block and a poll sure to see it.
+constexpr int kFlagMargin = 2;
 
 template <int NB>
 struct MfmaGeom {
@@ -96,60 +107,68 @@ struct MfmaGeom {
     static constexpr int kStride = 4 * ((2 * NB + 3) / 4);
     // The four ring slots are rewritten four blocks later, after the read.
     static_assert(2 * NB - 1 + kUnroll > kStride, "ring slot reuse");
+    // Super-steps from finishing block v (at v + 2NB - 1) to publishing it.
+    static constexpr int kPubOff = 2 * NB + kPubWait + 1;
 };
 
-// Where one super-step's memory operations go in its stream of 4*NB*R
-// products (the last band's first): after product k comes operation k, in
-// the order
-//   poll of the previous segment's flag (1), loads of input block sp+3
-//   (2R), loads of window matrices (2NB), then per row block r the two
-//   stores of the finished block and the ring write (3R, no earlier than
-//   two products after that row's last product),
-// and operations past the last product follow it.  The flag store that
-// publishes the previous super-step's block ends the super-step.  Every
-// working wave issues all of them (a role it does not have gets an empty
-// descriptor: loads return 0, stores are dropped), so no branch surrounds
-// a memory operation and the compiler's wait counts are exact.
+// One super-step of a wave: 4*NB*R products, the last band's first, with
+// its memory operations between them (StepOps::kind of position k follows
+// product k; positions past the last product follow it):
+//   vector memory: the flag poll, 2*kSlots loads of input block sp+3 (this
+//   wave's row blocks), 2*NB loads of window matrices, 2*kSlots stores of
+//   the finished block of the super-step before (this wave's row blocks),
+//   and after the products one flag store;
+//   LDS: before the products, the first band's input (R reads), the block
+//   to store (kSlots reads) and the input loaded two super-steps ago
+//   (kSlots writes); among the products, the last band's finished block
+//   into this wave's ring (R writes, two products after their row's last
+//   product).
+// Every wave issues the same vector memory operations in every super-step
+// (a role it does not have gets an empty descriptor: loads return 0,
+// stores are dropped), so no branch surrounds one and the compiler's wait
+// counts are exact; the publication wait counts this sequence.
 template <int NB, int R>
 struct StepOps {
+    static constexpr int kSlots = (R + kWaves - 1) / kWaves;  // row blocks per wave
     static constexpr int kProducts = 4 * NB * R;
     static constexpr int kPoll = 0;
-    static constexpr int kIn = 1;                // 2R loads
-    static constexpr int kQ = kIn + 2 * R;       // 2NB loads
-    static constexpr int kOut0 = (kQ + 2 * NB > 3 * R + 2) ? kQ + 2 * NB : 3 * R + 2;
-    static constexpr int kEnd = kOut0 + 3 * R;   // one past the last operation
-    // vector memory operations after the last store of block w (stored in
-    // super-step s) up to the flag store of super-step s+1
-    static constexpr int kAfterStores = 1 + (1 + 2 * R + 2 * NB + 2 * R);
+    static constexpr int kLoad = 1;                     // 2*kSlots
+    static constexpr int kQ = kLoad + 2 * kSlots;       // 2*NB
+    static constexpr int kStore = kQ + 2 * NB;          // 2*kSlots
+    static constexpr int kRing = (kStore + 2 * kSlots > 3 * R + 2) ? kStore + 2 * kSlots : 3 * R + 2;  // R
+    static constexpr int kEnd = kRing + R;
+    static constexpr int kPerStep = 1 + 2 * kSlots + 2 * NB + 2 * kSlots + 1;
+    // vector memory operations issued after the stores of super-step s up
+    // to the end of super-step s + kPubWait
+    static constexpr int kAfterStores = 1 + kPubWait * kPerStep;
     static_assert(kAfterStores < 64, "publication count");
 };
 
-// Descriptor over the 8 columns of block v (8v-7 .. 8v) of A, clipped to
+// Descriptor over the 8 columns of block v (8v .. 8v+7) of A, clipped to
 // [0, n), or an empty one if !on: lanes whose column lies outside get 0 on
-// loads and are dropped on stores.  A lane's byte offset within it is its
-// fixed part (column 8v-7 + g4 + 4e relative to 8v-7, and its row) plus
-// `shift` = (8v-7 - first column of the descriptor) * column stride.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const MfmaArgs &a, int v, bool on, int &shift)
+// loads and are dropped on stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const MfmaArgs &a, int v, bool on)
 {
-    // (readfirstlane: the clamp below is selected as a VALU instruction,
-    // and a descriptor left in VGPRs costs a loop around every access)
-    const int first = kSeq * v - (kSeq - 1);
-    const int lo = uniform(first < 0 ? 0 : first);
-    const int hi = kSeq * v + 1 < a.n ? kSeq * v + 1 : a.n;  // one past the last column
-    shift = uniform((int)((int64_t)(first - lo) * (int64_t)a.ldab));
-    const uint32_t bytes = (uint32_t)uniform(on && hi > lo ? (int)((uint64_t)(hi - lo) * a.ldab) : 0);
-    return make_rsrc(a.A + (uint64_t)lo * a.ldab, bytes);
+    const int lo = kSeq * v;
+    const int hi = lo + kSeq < a.n ? lo + kSeq : a.n;
+    const uint32_t bytes = (uint32_t)uniform(on && v >= 0 && hi > lo ? (int)((uint64_t)(hi - lo) * a.ldab) : 0);
+    return make_rsrc(a.A + (uint64_t)(int64_t)lo * a.ldab, bytes);
 }
 
 template <int NB, int R>
-__global__ __launch_bounds__(256, 1) void sweep_mfma(MfmaArgs a)
+__global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
 {
     using Ops = StepOps<NB, R>;
-    constexpr int kStride = MfmaGeom<NB>::kStride;
-    static_assert(kPubLag == 1, "publication count");
+    using Geom = MfmaGeom<NB>;
+    constexpr int kStride = Geom::kStride;
+    constexpr int kS = Ops::kSlots;
+    constexpr int kBlk = R * 64 * 2;  // doubles of one block (a ring or stage slot)
     extern __shared__ __align__(16) char lds_raw[];
     typedef __attribute__((address_space(3))) double lds_f64;
-    lds_f64 *ring = (lds_f64 *)(__attribute__((address_space(3))) char *)lds_raw;
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
+    // [kWaves rings + 1 stage][4 slots][R][64 lanes][2]
+    lds_f64 *lds = (lds_f64 *)(__attribute__((address_space(3))) char *)lds_raw;
 
     const int lane = threadIdx.x & 63;
     const int g4 = lane >> 4;
@@ -158,59 +177,59 @@ __global__ __launch_bounds__(256, 1) void sweep_mfma(MfmaArgs a)
     const int g = a.remap ? (p & 7) * (a.nwg >> 3) + (p >> 3) : p;
     const int tile = g / a.nseg;
     const int seg = g - tile * a.nseg;
-    const int chunk = seg * a.waves + wv;
-    const int active_waves = a.nchunks - seg * a.waves < a.waves ? a.nchunks - seg * a.waves : a.waves;
+    const int chunk = seg * kWaves + wv;
+    const int active = a.nchunks - seg * kWaves < kWaves ? a.nchunks - seg * kWaves : kWaves;
     const int nwin = a.nwin;
     const int pre = kUnroll + seg * a.seg_delay;
     const int off = pre + wv * kStride;
-    const int T = (pre + (a.waves - 1) * kStride + 2 * NB - 1 + nwin + 1 + kUnroll - 1) & ~(kUnroll - 1);
-    // The ring starts zeroed: a wave reads its slots before the previous
-    // wave first writes them (the products there use zero window matrices,
-    // and 0 * x is 0 only for finite x).
-    for (int x = (int)threadIdx.x; x < a.waves * kUnroll * R * 2 * 64; x += (int)blockDim.x)
-        ring[x] = 0.0;
+    const int off_out = pre + (active - 1) * kStride;
+    const int T = (pre + (kWaves - 1) * kStride + 2 * NB + nwin + kUnroll - 1) & ~(kUnroll - 1);
+    const bool in_wait = seg > 0;
+    const bool publish = seg * kWaves + active < a.nchunks;
+
+    // LDS starts zeroed: a wave reads ring and stage slots before they are
+    // first written (the products there use zero window matrices, and 0 * x
+    // is 0 only for finite x).
+    for (int x = (int)threadIdx.x; x < (kWaves + 1) * kUnroll * kBlk; x += (int)blockDim.x)
+        lds[x] = 0.0;
     __syncthreads();
 
-    if (wv >= active_waves) {  // no chunk: only the barriers
-        idle_groups(T);
-        return;
-    }
-    const bool in_global = wv == 0;
-    const bool in_wait = in_global && seg > 0;
-    const bool out_global = wv == active_waves - 1;
-    const bool publish = out_global && chunk + 1 < a.nchunks;
-
-    // Fixed part of this lane's byte offsets within a block, per row block
-    // and column group e (columns g4 + 4e of the block); rows past m get an
-    // offset past every descriptor's range (the planner keeps 9 columns of
-    // A below 2^30 bytes), so their stores are dropped.
+    // This wave's row blocks for loads and stores: r = wv + kWaves*i.  Byte
+    // offset of (row, column 8v + g4 + 4e) from column 8v; rows past m and
+    // row blocks past R get an offset past every descriptor's range (the
+    // planner keeps 8 columns of A below 2^30 bytes).
     const int64_t row0 = (int64_t)tile * R * 16 + (lane & 15);
-    int voff[R][2];
+    int voff[kS][2];
+    int slot_r[kS];  // row block in a slot, clamped to R-1 for reads
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t ro = row0 + 16 * r < a.m ? (uint32_t)((row0 + 16 * r) * 8) : 0x80000000u;
+    for (int i = 0; i < kS; ++i) {
+        const int r = wv + kWaves * i;
+        slot_r[i] = r < R ? r : R - 1;
+        const bool ok = r < R && row0 + 16 * r < a.m;
+        const uint32_t ro = ok ? (uint32_t)((row0 + 16 * r) * 8) : 0x80000000u;
 #pragma unroll
         for (int e = 0; e < 2; ++e)
-            voff[r][e] = (int)(ro + (uint32_t)((g4 + 4 * e) * a.ldab));
+            voff[i][e] = (int)(ro + (uint32_t)((g4 + 4 * e) * a.ldab));
     }
 
-    // Window matrices of this wave's bands: one descriptor per band.
-    __amdgpu_buffer_rsrc_t qrs[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        qrs[i] = make_rsrc(a.q + ((uint64_t)(chunk * NB + i) * (nwin + 1)) * kQBytes,
-                           (uint32_t)((nwin + 1) * kQBytes));
+    // Window matrices of this wave's bands (none for a wave past the last
+    // chunk): [band][window -1 .. nwin-1][64 lanes][4 doubles].
+    const uint64_t qband0 = a.q + (uint64_t)(chunk * NB) * (uint64_t)(nwin + 1) * kQBytes;
+    const bool has_bands = chunk < a.nchunks;
     const int qvoff = lane * 32;
 
-    int *flag_in = a.flags + (int64_t)tile * a.nseg + (seg - 1);
-    int *flag_out = a.flags + (int64_t)tile * a.nseg + seg;
+    int *flag_in = a.flags + ((int64_t)tile * a.nseg + (seg - 1)) * kMfmaFlagStride;
+    int *flag_out = a.flags + ((int64_t)tile * a.nseg + seg) * kMfmaFlagStride;
     const __amdgpu_buffer_rsrc_t flag_in_rs = make_rsrc((uint64_t)flag_in, in_wait ? 4u : 0u);
-    int limit = a.spin_limit, timed_out = 0, known = 0, polled = 0;
+    int limit = a.spin_limit, timed_out = 0, known = 0;
+    int polled[kUnroll] = {0, 0, 0, 0};
 
-    // Ring of wave j -> j+1: [4 slots][R][2 elements][64 lanes] per wave
-    // (the first wave reads its own ring, and ignores what it reads).
-    lds_f64 *ring_in = ring + (int64_t)(wv > 0 ? wv - 1 : 0) * (kUnroll * R * 2 * 64) + lane;
-    lds_f64 *ring_out = ring + (int64_t)wv * (kUnroll * R * 2 * 64) + lane;
+    // First band's input: the stage (first wave) or the previous wave's ring.
+    lds_f64 *const stage = lds + (int64_t)kWaves * kUnroll * kBlk;
+    const lds_f64x2 *nin_src = (const lds_f64x2 *)(wv == 0 ? stage : lds + (int64_t)(wv - 1) * kUnroll * kBlk) + lane;
+    lds_f64x2 *ring_out = (lds_f64x2 *)(lds + (int64_t)wv * kUnroll * kBlk) + lane;
+    const lds_f64x2 *ring_last = (const lds_f64x2 *)(lds + (int64_t)(active - 1) * kUnroll * kBlk) + lane;
+    lds_f64x2 *stage_w = (lds_f64x2 *)stage + lane;
 
     f64x4 D[2][NB][R];
 #pragma unroll
@@ -220,13 +239,13 @@ __global__ __launch_bounds__(256, 1) void sweep_mfma(MfmaArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 D[b2][i][r] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double IN[kUnroll][R][2];  // input blocks of the first wave, 3 ahead
-    double Qr[kUnroll][NB][4]; // window matrices, 3 ahead
+    double IN[kUnroll][kS][2];  // this wave's part of input block v, slot v & 3
+    double Qr[kUnroll][NB][4];  // window matrices, 3 ahead
 #pragma unroll
     for (int x = 0; x < kUnroll; ++x) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            IN[x][r][0] = IN[x][r][1] = 0.0;
+        for (int i = 0; i < kS; ++i)
+            IN[x][i][0] = IN[x][i][1] = 0.0;
 #pragma unroll
         for (int i = 0; i < NB; ++i)
             Qr[x][i][0] = Qr[x][i][1] = Qr[x][i][2] = Qr[x][i][3] = 0.0;
@@ -235,73 +254,77 @@ __global__ __launch_bounds__(256, 1) void sweep_mfma(MfmaArgs a)
     for (int t = 0; t < T; t += kUnroll) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int sp = t + u - off;  // wave-local super-step; sp % 4 == u % 4
+            const int tt = t + u - pre;  // workgroup-local super-step; tt % 4 == u % 4
+            const int sp = t + u - off;  // wave-local super-step;      sp % 4 == u % 4
             const int cur = u & 1, prv = cur ^ 1;
-            // 1. A later segment's first wave loads input block sp + 3 once
-            // the previous segment has published it: the poll issued last
-            // super-step normally says so; otherwise wait here.
+            // 1. A later segment loads input block tt+3 once the previous
+            // segment has published it: the poll of kPollLag super-steps
+            // ago normally says so; otherwise wait here.
             if (in_wait) {
-                const int v = sp + 3;
+                const int v = tt + 3;
                 const int need = (v + 1 < nwin ? v + 1 : nwin) + a.wait_bias;
-                const int seen = uniform(polled);
+                const int seen = uniform(polled[u]);
                 known = known > seen ? known : seen;
                 if (known < need)
                     known = wait_flag(flag_in, need - 1, limit, timed_out);
             }
-            // 2. Descriptors of the super-step: input block sp+3 (first
-            // wave), finished block sp-2NB+1 of the last band (last wave).
-            int in_shift, out_shift;
-            const __amdgpu_buffer_rsrc_t in_rs = block_rsrc(a, sp + 3, in_global, in_shift);
-            const int wo = sp - 2 * NB + 1;
-            const __amdgpu_buffer_rsrc_t out_rs = block_rsrc(a, wo, out_global && wo >= 0 && wo <= nwin - 1, out_shift);
-            // New columns for band 0, block sp: from A (first wave, loaded
-            // three super-steps ago) or the previous wave's ring slot, read
-            // here and selected where band 0 uses them (the reads are
-            // volatile, so they are issued in every wave and the choice is
-            // a select, not a branch).
-            double ringv[R][2];
+            // 2. Descriptors of the super-step.
+            const __amdgpu_buffer_rsrc_t in_rs = block_rsrc(a, tt + 3, true);
+            const int wo = t + u - off_out - 2 * NB;  // block to store
+            const __amdgpu_buffer_rsrc_t out_rs = block_rsrc(a, wo, wo <= nwin - 1);
+            __amdgpu_buffer_rsrc_t qrs[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int wq = sp + 2 - 2 * i;  // band i's window three super-steps on
+                const bool ok = has_bands && wq >= -1 && wq <= nwin - 1;
+                qrs[i] = make_rsrc(qband0 + ((uint64_t)i * (nwin + 1) + (uint64_t)(ok ? wq + 1 : 0)) * kQBytes,
+                                   ok ? (uint32_t)kQBytes : 0u);
+            }
+            // 3. LDS before the products: the first band's input block sp,
+            // the block to store, and the stage of input block tt+1.
+            f64x2 nin[R];
 #pragma unroll
             for (int r = 0; r < R; ++r)
+                nin[r] = nin_src[(u * R + r) * 64];
+            f64x2 outv[kS];
 #pragma unroll
-                for (int e = 0; e < 2; ++e)
-                    ringv[r][e] = ((volatile lds_f64 *)ring_in)[((u * R + r) * 2 + e) * 64];
+            for (int i = 0; i < kS; ++i)
+                outv[i] = ring_last[((((u - 2 * NB) & 3) * R) + slot_r[i]) * 64];
+#pragma unroll
+            for (int i = 0; i < kS; ++i)
+                if (wv + kWaves * i < R)
+                    stage_w[(((u + 1) & 3) * R + wv + kWaves * i) * 64] = f64x2{IN[(u + 1) & 3][i][0], IN[(u + 1) & 3][i][1]};
             compiler_fence();
             __builtin_amdgcn_sched_barrier(0);
 
             // Memory operation k of the super-step (compile-time k).
             auto memop = [&](const int k) {
                 if (k == Ops::kPoll) {
-                    polled = (int)__builtin_amdgcn_raw_buffer_load_b32(flag_in_rs, 0, 0, kPolicyDevice);
-                } else if (k >= Ops::kIn && k < Ops::kQ) {
-                    const int r = (k - Ops::kIn) >> 1, e = (k - Ops::kIn) & 1;
-                    IN[(u + 3) & 3][r][e] = buf_load<kPolicyDevice>(double(), in_rs, voff[r][e] + in_shift);
-                } else if (k >= Ops::kQ && k < Ops::kQ + 2 * NB) {
-                    // band i's window sp+2-2i, used three super-steps later
-                    // (outside -1 .. nwin-1: zeros)
+                    polled[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(flag_in_rs, 0, 0, kPolicyDevice);
+                } else if (k >= Ops::kLoad && k < Ops::kQ) {
+                    const int i = (k - Ops::kLoad) >> 1, e = (k - Ops::kLoad) & 1;
+                    IN[(u + 3) & 3][i][e] = buf_load<kPolicyDevice>(double(), in_rs, voff[i][e]);
+                } else if (k >= Ops::kQ && k < Ops::kStore) {
                     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
                     const int i = (k - Ops::kQ) >> 1, h = (k - Ops::kQ) & 1;
-                    const int vo = (sp + 2 - 2 * i + 1) * kQBytes + qvoff + 16 * h;
-                    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(qrs[i], vo, 0, kPolicyL2);
+                    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(qrs[i], qvoff + 16 * h, 0, kPolicyL2);
                     Qr[(u + 3) & 3][i][2 * h] = __builtin_bit_cast(double, (unsigned long long)q.x | ((unsigned long long)q.y << 32));
                     Qr[(u + 3) & 3][i][2 * h + 1] = __builtin_bit_cast(double, (unsigned long long)q.z | ((unsigned long long)q.w << 32));
-                } else if (k >= Ops::kOut0 && k < Ops::kEnd) {
-                    const int r = (k - Ops::kOut0) / 3, o = (k - Ops::kOut0) % 3;
+                } else if (k >= Ops::kStore && k < Ops::kStore + 2 * kS) {
+                    const int i = (k - Ops::kStore) >> 1, e = (k - Ops::kStore) & 1;
+                    buf_store<kPolicyDevice>(e == 0 ? outv[i].x : outv[i].y, out_rs, voff[i][e]);
+                } else if (k >= Ops::kRing && k < Ops::kEnd) {
+                    const int r = k - Ops::kRing;
                     const f64x4 &d = D[cur][NB - 1][r];
-                    if (o < 2) {
-                        buf_store<kPolicyDevice>(o == 0 ? d.x : d.y, out_rs, voff[r][o] + out_shift);
-                    } else {
-                        ring_out[((((u - 2 * NB + 1) & 3) * R + r) * 2 + 0) * 64] = d.x;
-                        ring_out[((((u - 2 * NB + 1) & 3) * R + r) * 2 + 1) * 64] = d.y;
-                    }
+                    ring_out[((((u - 2 * NB + 1) & 3) * R) + r) * 64] = f64x2{d.x, d.y};
                 }
             };
 
-            // 3. Products, last band first: band i runs window sp-1-2i on
+            // 4. Products, last band first: band i runs window sp-1-2i on
             // its own in-flight columns and band i-1's block of the last
             // super-step.  Outside the band's windows the window matrix is
             // zero, so the band's state before its first window and what it
-            // passes on after its last one are zero (every operand is
-            // finite: loads outside A return 0 and the ring starts zeroed).
+            // passes on after its last one are zero.
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi) {
                 const int i = NB - 1 - bi;
@@ -316,7 +339,7 @@ __global__ __launch_bounds__(256, 1) void sweep_mfma(MfmaArgs a)
                         else if (s == 1)
                             b = D[prv][i][r].w;
                         else if (i == 0)
-                            b = in_global ? IN[u][r][s - 2] : ringv[r][s - 2];
+                            b = s == 2 ? nin[r].x : nin[r].y;
                         else
                             b = s == 2 ? D[prv][ip][r].x : D[prv][ip][r].y;
                         D[cur][i][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(
@@ -330,26 +353,28 @@ __global__ __launch_bounds__(256, 1) void sweep_mfma(MfmaArgs a)
                 memop(k);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            // 4. Publish the block stored last super-step, once every
-            // vector memory operation but the kAfterStores issued since its
-            // stores has completed.
+            // 5. Publication: the first wave publishes the block whose
+            // stores every wave covered with its wait of the last
+            // super-step; every wave covers the stores of kPubWait
+            // super-steps ago.
             compiler_fence();
             {
-                const int wp = sp - 2 * NB;
-                const bool pub = publish && wp >= 0 && wp <= nwin - 1;
-                if (publish)
-                    wait_vmem_at_most<Ops::kAfterStores>();
-                compiler_fence();
+                const int wp = t + u - off_out - Geom::kPubOff;
+                const bool pub = publish && wv == 0 && wp >= 0 && wp <= nwin - 1;
                 __builtin_amdgcn_raw_buffer_store_b32((unsigned)(wp + 1), make_rsrc((uint64_t)flag_out, pub ? 4u : 0u),
                                                       0, 0, kPolicyDevice);
+                if (publish)
+                    wait_vmem_at_most<Ops::kAfterStores>();
             }
-            // 5. Ring writes of this super-step are complete; all waves meet.
+            // 6. LDS writes of this super-step are complete; all waves meet.
             group_barrier();
         }
     }
     if (publish) {
         wait_vmem_at_most<0>();
-        __hip_atomic_store(flag_out, nwin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        group_barrier();
+        if (wv == 0)
+            __hip_atomic_store(flag_out, nwin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (timed_out)
         record_timeout(a.status, timed_out);
@@ -375,19 +400,20 @@ __global__ __launch_bounds__(64) void mfma_prep_q(const T *__restrict__ C, int64
 #pragma unroll
     for (int c = 0; c < kWin; ++c)
         v[c] = c == row ? 1.0 : 0.0;
-    if (w >= 0) {
+    {
 #pragma unroll
         for (int tau = 0; tau < kSeq; ++tau) {
 #pragma unroll
             for (int qq = 0; qq < kSeq; ++qq) {
-                const int64_t j = (int64_t)kSeq * w + tau - qq;
+                const int64_t j = (int64_t)kSeq * w + kSeq - 1 + tau - qq;
                 const int64_t pp = band * kSeq + qq;
                 double c = 1.0, s = 0.0;
                 if (j >= 0 && j <= n - 2 && pp < k) {
                     c = (double)C[j + pp * ldc];
                     s = (double)S[j + pp * lds];
                 }
-                const int uu = tau - qq + kSeq - 1;
+                const int uu = kSeq - 1 + tau - qq;  // j - 8w, compile-time
+
                 const double x = v[uu], y = v[uu + 1];
                 v[uu] = __builtin_fma(c, x, s * y);
                 v[uu + 1] = __builtin_fma(c, y, -(s * x));
@@ -421,7 +447,7 @@ hipError_t go_mfma(const Plan &p, double *A, const char *ws, hipStream_t st)
     a.q = (uint64_t)(ws + p.off_coef);
     a.flags = (int *)(ws + p.off_flags);
     a.status = p.status;
-    sweep_mfma<NB, R><<<p.nwg, p.waves * kWave, p.lds_bytes, st>>>(a);
+    sweep_mfma<NB, R><<<p.nwg, kWaves * kWave, p.lds_bytes, st>>>(a);
     return hipGetLastError();
 }
 
@@ -436,24 +462,28 @@ bool mfma_shape_supported(int nb_wave, int rows)
 
 int mfma_wave_stride(int nb_wave) { return 4 * ((2 * nb_wave + 3) / 4); }
 
-int mfma_seg_delay(int waves, int nb_wave)
+int mfma_waves() { return kWaves; }
+
+int mfma_seg_delay(int nb_wave)
 {
-    // The first wave of a later segment loads block v+3 at its super-step
-    // v, on the strength of the flag poll it issued one super-step before;
-    // the previous segment's last wave stored that block at
-    // (waves-1)*stride + 2NB-1 + v+3 and publishes it kPubLag super-steps
-    // later, and a poll kFlagMargin super-steps after that sees it.
-    const int need = mfma_wave_stride(nb_wave) * (waves - 1) + 2 * nb_wave + 3 + kPubLag + kFlagMargin;
+    // The waves of a later segment load block v at their super-step v-3
+    // (from the segment's start) on the strength of a flag poll issued
+    // kPollLag super-steps before; the previous segment finishes block v
+    // in its last wave at (kWaves-1)*stride + v + 2NB-1, publishes it
+    // 2 + kPubWait super-steps later, and a poll kFlagMargin super-steps
+    // after that sees it.
+    const int pub = 2 * nb_wave + kPubWait + 1;
+    const int need = mfma_wave_stride(nb_wave) * (kWaves - 1) + pub + 3 + kPollLag + kFlagMargin;
     return 4 * ((need + 3) / 4);
 }
 
-size_t mfma_lds_bytes(int waves, int rows)
+size_t mfma_lds_bytes(int rows)
 {
-    // one ring per wave (the last wave's is written and never read)
-    return (size_t)waves * kUnroll * rows * 2 * 64 * sizeof(double);
+    // a ring per wave and the input stage: [5][4 slots][rows][64 lanes][2 doubles]
+    return (size_t)(kWaves + 1) * kUnroll * rows * 64 * 2 * sizeof(double);
 }
 
-hipError_t mfma_occupancy(int nb_wave, int rows, int waves, size_t lds, int *blocks)
+hipError_t mfma_occupancy(int nb_wave, int rows, size_t lds, int *blocks)
 {
     const void *fn = nullptr;
 #define ROTSEQ_MFMA_FN(NBV, RV) \
@@ -468,7 +498,7 @@ hipError_t mfma_occupancy(int nb_wave, int rows, int waves, size_t lds, int *blo
 #undef ROTSEQ_MFMA_FN
     if (fn == nullptr)
         return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, waves * kWave, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kWaves * kWave, lds);
 }
 
 hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t st)
@@ -484,7 +514,7 @@ hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *w
     else
         mfma_prep_q<float><<<blocks, B, 0, st>>>((const float *)C, p.ldc, (const float *)S, p.lds,
                                                  (int)p.n, p.k, nbands, p.mfma_nwin, q);
-    const int64_t words = (int64_t)p.mfma_tiles * p.mfma_nseg;
+    const int64_t words = (int64_t)p.mfma_tiles * p.mfma_nseg * kMfmaFlagStride;
     return launch_zero((int *)((char *)ws + p.off_flags), words, st);
 }
 

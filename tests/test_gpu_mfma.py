@@ -6,8 +6,8 @@ v_mfma_f64_16x16x4f64; results agree with Algorithm 2 up to rounding, so
 the bar is the FP64 tolerance, 1e-13 relative Frobenius error.  Shapes
 cover one row tile and many, ragged row tiles (m not a multiple of 16),
 n below one window, k below, at and above a band, padded leading
-dimensions, every compiled wave shape, one to four waves per workgroup (so
-chains crossing workgroups through A and flags), padded bands, left
+dimensions, every compiled wave shape, chains crossing workgroups through
+A and flags, waves without bands, padded bands, left
 application on the packed copy, the automatic choice at the full target
 size, the error path of a wait that gives up, and refused combinations.
 """
@@ -69,18 +69,19 @@ SHAPES = [35, 34, 32, 24, 22, 14, 12]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("waves", [1, 2, 3, 4])
-def test_mfma_shapes_and_workgroups(shape, waves):
-    """Every compiled (bands, row blocks) per wave with 1-4 waves per
-    workgroup: 11 bands (padded to the chunk size), 13 row blocks with a
-    ragged last one, so tiles are partial and chains cross workgroups."""
-    say(f"mfma shape={shape} waves={waves}")
-    pb = make_problem(200, 301, 83, seed=shape * 10 + waves, lda=203)
-    info = rs.launch_describe("d", 200, 301, 83, lda=203, opts={"kernel": MFMA, "shape": shape,
-                                                              "waves": waves})
-    assert info["kernel"] == MFMA and info["waves"] == waves
+@pytest.mark.parametrize("k", [83, 8, 200])
+def test_mfma_shapes_and_workgroups(shape, k):
+    """Every compiled (bands, row blocks) per wave on 4-wave workgroups: k =
+    83 is 11 bands (padded to the chunk size), so tiles are partial and
+    chains cross workgroups; k = 8 leaves waves without bands (they still
+    load and store their row blocks); k = 200 is 25 bands, up to 9
+    segments.  200 rows (13 row blocks, the last ragged), lda padded."""
+    say(f"mfma shape={shape} k={k}")
+    pb = make_problem(200, 301, k, seed=shape * 10 + k, lda=203)
+    info = rs.launch_describe("d", 200, 301, k, lda=203, opts={"kernel": MFMA, "shape": shape})
+    assert info["kernel"] == MFMA and info["waves"] == 4
     assert info["bands_per_wave"] == shape // 10 and info["rows_per_wave"] == 16 * (shape % 10)
-    got, ref, pad_ok = run_mfma(pb, {"kernel": MFMA, "shape": shape, "waves": waves})
+    got, ref, pad_ok = run_mfma(pb, {"kernel": MFMA, "shape": shape})
     assert pad_ok
     assert relerr(got, ref, pb.A) <= TOL["f64"]
 
@@ -142,6 +143,7 @@ def test_mfma_forced_at_the_target_size_sampled_rows():
                                         ({"kernel": MFMA, "inverse": 1}, "f64"),
                                         ({"kernel": MFMA, "arith": rs.ARITH_EXACT}, "f64"),
                                         ({"kernel": MFMA, "band": 4}, "f64"),
+                                        ({"kernel": MFMA, "waves": 2}, "f64"),
                                         ({"kernel": MFMA, "shape": 99}, "f64")])
 def test_mfma_refuses_unsupported(opts, dtype):
     import torch
@@ -156,9 +158,9 @@ def test_mfma_refuses_unsupported(opts, dtype):
 
 
 def test_mfma_wait_timeout_reported():
-    """One wave per workgroup puts every band chunk in its own workgroup;
-    with unreachable waits every later chunk gives up and the status word
-    says so; the kernels still complete."""
+    """One band per wave: 6 bands are two segments, so the second
+    workgroup of each tile waits on the first; with unreachable waits it
+    gives up and the status word says so; the kernels still complete."""
     import torch
     say("mfma forced wait time-out")
     pb = make_problem(100, 120, 48, seed=41)
@@ -167,12 +169,12 @@ def test_mfma_wait_timeout_reported():
     assert rs.device_status(reset=True) == 0
     rs.test_set_waits(1, unreachable=True)
     try:
-        rs.rotseq(A, C, S, opts={"kernel": MFMA, "shape": 12, "waves": 1})
+        rs.rotseq(A, C, S, opts={"kernel": MFMA, "shape": 12})
         torch.cuda.synchronize()
         st = rs.device_status(reset=True)
     finally:
         rs.test_set_waits(0, unreachable=False)
     assert st & 0xff == 5, hex(st)
-    rs.rotseq(A, C, S, opts={"kernel": MFMA, "shape": 12, "waves": 1})
+    rs.rotseq(A, C, S, opts={"kernel": MFMA, "shape": 12})
     torch.cuda.synchronize()
     assert rs.device_status(reset=True) == 0

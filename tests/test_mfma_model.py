@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from mfma_model import (FLAG_MARGIN, KB, PUB_LAG, band_model, block_cols, nwin_of, qsw_layout, schedule_events,
+from mfma_model import (FLAG_MARGIN, KB, POLL_LAG, band_model, block_cols, nwin_of, qsw_layout, schedule_events,
                         seg_delay, sweep_model, total_steps, wave_stride, window_q)
 from paper_2412_01852_amd.inputs import make_problem
 
@@ -25,7 +25,9 @@ def test_windowed_sweep_equals_oracle(m, n, k):
 
 def test_window_matrices_orthogonal_and_banded():
     """Q(band, w) is orthogonal, and Q[i, c] = 0 for i > c + 8: a band of 8
-    sequences moves an input column at most 8 places to the left."""
+    sequences moves an input column at most 8 places to the left.  Window
+    -1 leaves the virtual columns -8..-1 (rows and columns 0..7 of Q) alone,
+    and a window past the last column is the identity."""
     pb = make_problem(1, 50, 20, seed=5)
     C, S = np.asarray(pb.C), np.asarray(pb.S)
     for band in range(3):
@@ -34,7 +36,10 @@ def test_window_matrices_orthogonal_and_banded():
             assert np.allclose(Q.T @ Q, np.eye(16), atol=1e-14)
             i, c = np.indices(Q.shape)
             assert np.all(Q[i > c + KB] == 0.0)
-    assert np.array_equal(window_q(C, S, 50, 20, 0, -1), np.eye(16))
+        Qm = window_q(C, S, 50, 20, band, -1)
+        assert np.array_equal(Qm[:KB, :], np.eye(16)[:KB, :])
+        assert np.array_equal(Qm[:, :KB], np.eye(16)[:, :KB])
+    assert np.array_equal(window_q(C, S, 50, 20, 0, nwin_of(50) + 1), np.eye(16))
 
 
 def test_blocks_cover_every_column_once():
@@ -44,6 +49,8 @@ def test_blocks_cover_every_column_once():
         assert np.array_equal(np.sort(real), np.arange(n))
         # the block after the last window holds only virtual columns
         assert block_cols(nwin_of(n))[0] >= n
+        # the last window ends at or after the band's last step, n + 5
+        assert KB * (nwin_of(n) - 1) + 2 * KB - 2 >= n + 5
 
 
 def test_single_band_mutant_caught():
@@ -70,55 +77,58 @@ def test_qsw_layout_matches_matrix_operand():
             assert L[lane, s] == Q[4 * s + lane // 16, lane % 16]
 
 
-@pytest.mark.parametrize("waves,nb_wave", [(4, 3), (4, 2), (4, 1), (2, 3), (1, 1), (3, 3)])
+@pytest.mark.parametrize("nb_wave", [1, 2, 3])
+@pytest.mark.parametrize("active", [1, 2, 3, 4])
 @pytest.mark.parametrize("nwin", [1, 2, 5, 17])
-def test_schedule_dependencies(waves, nb_wave, nwin):
-    """Within a workgroup: band i of a wave consumes band i-1's output of
-    the previous super-step (so the bands of a super-step are
-    independent); ring blocks are written
-    in a strictly earlier super-step than they are read and not rewritten
-    (4 slots) until after the read; every event lies inside the
-    workgroup's super-step count."""
-    ev = schedule_events(waves, nb_wave, nwin)
-    T = total_steps(waves, nb_wave, nwin)
+def test_schedule_dependencies(nb_wave, active, nwin):
+    """Within a workgroup: band i consumes band i-1's block of the previous
+    super-step (so the bands of a super-step are independent); every ring,
+    stage and store slot is written in a strictly earlier super-step than
+    it is read and not rewritten (4 slots) until after that read; loads are
+    two super-steps old when staged; every event lies inside the
+    workgroup's super-steps."""
+    ev = schedule_events(nb_wave, nwin, active=active)
+    T = total_steps(nb_wave, nwin)
     mf = {(e[1], e[2], e[3]): e[4] for e in ev if e[0] == "mfma"}
-    for (j, i, w), s in mf.items():
-        assert 0 <= s < T
+    for (j, i, w), t in mf.items():
         if i > 0 and w + 1 <= nwin - 1:
-            assert mf[(j, i - 1, w + 1)] == s - 1  # previous super-step
-    writes = {}
+            assert mf[(j, i - 1, w + 1)] == t - 1
+    ring_w = {(e[1], e[2]): e[4] for e in ev if e[0] == "ring_w"}
     for e in ev:
-        if e[0] == "ring_w":
-            writes[(e[1], e[2])] = e[4]
+        if e[0] == "ring_r":
+            _, j, v, slot, t = e
+            assert ring_w[(j - 1, v)] < t
+            assert ring_w.get((j - 1, v + 4), T) > t
+            assert mf[(j, 0, v - 1)] == t  # band 0 takes block v at window v-1
+    load = {e[1]: e[2] for e in ev if e[0] == "load"}
+    stage_w = {e[1]: e[3] for e in ev if e[0] == "stage_w"}
     for e in ev:
-        if e[0] != "ring_r":
-            continue
-        _, j, v, slot, s = e
-        ws = writes[(j - 1, v)]
-        assert ws < s, (j, v, ws, s)
-        nxt = writes.get((j - 1, v + 4))
-        if nxt is not None:
-            assert nxt > s, (j, v, nxt, s)
-        # band 0 of wave j uses block v at window v-1
-        assert mf[(j, 0, v - 1)] == s
+        if e[0] == "stage_r":
+            _, v, slot, t = e
+            assert load[v] + 2 <= stage_w[v] < t
+            assert stage_w.get(v + 4, T) > t
+            assert mf[(0, 0, v - 1)] == t
+    out = active - 1
     for e in ev:
-        if e[0] in ("out", "in", "ring_w", "ring_r"):
-            assert 0 <= e[-1] < T
+        if e[0] == "store":
+            _, v, slot, t = e
+            assert ring_w[(out, v)] < t < ring_w[(out, v + 4)] if (out, v + 4) in ring_w else ring_w[(out, v)] < t
+    for e in ev:
+        if e[0] in ("mfma", "ring_w", "ring_r", "stage_r", "store"):
+            assert 0 <= e[-1] < T, e
+        if e[0] in ("load", "stage_w"):
+            assert e[-1] < T, e  # loads before the segment's start fetch empty blocks
 
 
-@pytest.mark.parametrize("waves,nb_wave", [(4, 3), (4, 2), (4, 1), (2, 3)])
-def test_segment_handoff_margin(waves, nb_wave):
-    """The first wave of segment s+1 issues the loads of block v+3 at its
-    super-step v after checking the flag poll it issued one super-step
-    earlier; the last wave of segment s publishes block v+3 PUB_LAG
-    super-steps after storing it; the delay leaves FLAG_MARGIN super-steps
-    between the publication and that poll."""
+@pytest.mark.parametrize("nb_wave", [1, 2, 3])
+def test_segment_handoff_margin(nb_wave):
+    """The waves of segment s+1 load block v at their super-step v-3 using
+    a flag poll issued POLL_LAG super-steps earlier; segment s publishes v
+    at least FLAG_MARGIN super-steps before that poll."""
     nwin = 20
     for seg in (1, 2):
-        prod = {e[2]: e[3] for e in schedule_events(waves, nb_wave, nwin, seg - 1)
-                if e[0] == "out"}
-        cons = {e[2]: e[3] for e in schedule_events(waves, nb_wave, nwin, seg) if e[0] == "in"}
-        for v in range(0, nwin + 1):
-            poll_step = cons[v] - 3 - 1
-            assert poll_step >= prod[v] + PUB_LAG + FLAG_MARGIN, (seg, v)
-    assert seg_delay(waves, nb_wave) % 4 == 0 and wave_stride(nb_wave) % 4 == 0
+        pub = {e[1]: e[2] for e in schedule_events(nb_wave, nwin, seg - 1) if e[0] == "publish"}
+        load = {e[1]: e[2] for e in schedule_events(nb_wave, nwin, seg) if e[0] == "load"}
+        for v in range(0, nwin):
+            assert load[v] - POLL_LAG >= pub[v] + FLAG_MARGIN, (seg, v)
+    assert seg_delay(nb_wave) % 4 == 0 and wave_stride(nb_wave) % 4 == 0
