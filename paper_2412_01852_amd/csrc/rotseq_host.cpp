@@ -35,7 +35,7 @@ int64_t mfma_windows(int64_t n) { return (n + 7) / 8; }
 
 // Workspace of the matrix-instruction sweep's window matrices, for any
 // bands-per-wave choice (at most 2 padded bands), and of its flags.
-size_t mfma_q_bytes(int64_t n, int64_t k) { return (size_t)((k + 7) / 8 + 2) * (mfma_windows(n) + 1) * 2048; }
+size_t mfma_q_bytes(int64_t n, int64_t k) { return (size_t)((k + 7) / 8 + 2) * (mfma_windows(n) + 3) * 2048; }
 // One progress flag per (tile, segment), each on its own 128-byte line
 // (polled by one workgroup while another writes it through every
 // super-step; neighbours on one line would share that traffic).  Tiles are
@@ -227,6 +227,8 @@ double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
             const int64_t nseg = (nchunks + w - 1) / w;
             const int64_t nwg = tiles * nseg;
             if (nwg > INT32_MAX || nchunks * nb > nbands + 2)  // reserved window matrices
+                continue;
+            if ((int64_t)nb * (nwin + 3) * 2048 >= ((int64_t)1 << 31))  // a wave's window matrices
                 continue;
             const size_t lds = mfma_lds_bytes(rows);
             if (lds > d.max_lds)

@@ -81,7 +81,7 @@ struct MfmaArgs {
     int remap;       // 1: consecutive workgroups on one XCD
     int spin_limit;
     int wait_bias;
-    uint64_t q;      // [band][nwin+1][64 lanes][4 slabs] window matrices
+    uint64_t q;      // [band][nwin+3][64 lanes][4 slabs] window matrices -2 .. nwin (ends zero)
     int *flags;      // [tile][seg][32] blocks published by the segment (first int of 128 bytes)
     int *status;
 };
@@ -144,17 +144,6 @@ struct StepOps {
     static_assert(kAfterStores < 64, "publication count");
 };
 
-// Descriptor over the 8 columns of block v (8v .. 8v+7) of A, clipped to
-// [0, n), or an empty one if !on: lanes whose column lies outside get 0 on
-// loads and are dropped on stores.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const MfmaArgs &a, int v, bool on)
-{
-    const int lo = kSeq * v;
-    const int hi = lo + kSeq < a.n ? lo + kSeq : a.n;
-    const uint32_t bytes = (uint32_t)uniform(on && v >= 0 && hi > lo ? (int)((uint64_t)(hi - lo) * a.ldab) : 0);
-    return make_rsrc(a.A + (uint64_t)(int64_t)lo * a.ldab, bytes);
-}
-
 template <int NB, int R>
 __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
 {
@@ -213,9 +202,13 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
     }
 
     // Window matrices of this wave's bands (none for a wave past the last
-    // chunk): [band][window -1 .. nwin-1][64 lanes][4 doubles].
-    const uint64_t qband0 = a.q + (uint64_t)(chunk * NB) * (uint64_t)(nwin + 1) * kQBytes;
-    const bool has_bands = chunk < a.nchunks;
+    // chunk): [band][window -2 .. nwin][64 lanes][4 doubles], the first and
+    // last zero; a band's window w is read at scalar offset
+    // (band * (nwin+3) + clamp(w, -2, nwin) + 2) * kQBytes.
+    const int qwin = nwin + 3;
+    const __amdgpu_buffer_rsrc_t qrs = make_rsrc(
+        a.q + (uint64_t)(chunk * NB) * (uint64_t)qwin * kQBytes,
+        chunk < a.nchunks ? (uint32_t)(NB * qwin * kQBytes) : 0u);
     const int qvoff = lane * 32;
 
     int *flag_in = a.flags + ((int64_t)tile * a.nseg + (seg - 1)) * kMfmaFlagStride;
@@ -230,6 +223,20 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
     lds_f64x2 *ring_out = (lds_f64x2 *)(lds + (int64_t)wv * kUnroll * kBlk) + lane;
     const lds_f64x2 *ring_last = (const lds_f64x2 *)(lds + (int64_t)(active - 1) * kUnroll * kBlk) + lane;
     lds_f64x2 *stage_w = (lds_f64x2 *)stage + lane;
+
+    // Blocks loaded (tt + 3) and stored (t - off_out - 2NB) in the coming
+    // super-step, with their first columns' addresses.
+    const uint64_t blk_bytes = (uint64_t)kSeq * a.ldab;
+    const uint32_t full_bytes = (uint32_t)blk_bytes;
+    const uint32_t last_bytes = (uint32_t)((uint64_t)(a.n - kSeq * (nwin - 1)) * a.ldab);
+    int in_v = 3 - pre, out_v = -off_out - 2 * NB;
+    uint64_t in_base = a.A + (uint64_t)(int64_t)in_v * blk_bytes;
+    uint64_t out_base = a.A + (uint64_t)(int64_t)out_v * blk_bytes;
+    // Flag store of a super-step: real only in the first wave of a
+    // publishing workgroup, for blocks 0 .. nwin-1.
+    const __amdgpu_buffer_rsrc_t flag_on = make_rsrc((uint64_t)flag_out, publish && wv == 0 ? 4u : 0u);
+    const __amdgpu_buffer_rsrc_t flag_off = make_rsrc((uint64_t)flag_out, 0u);
+    int wp = -off_out - Geom::kPubOff;
 
     f64x4 D[2][NB][R];
 #pragma unroll
@@ -268,17 +275,22 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
                 if (known < need)
                     known = wait_flag(flag_in, need - 1, limit, timed_out);
             }
-            // 2. Descriptors of the super-step.
-            const __amdgpu_buffer_rsrc_t in_rs = block_rsrc(a, tt + 3, true);
-            const int wo = t + u - off_out - 2 * NB;  // block to store
-            const __amdgpu_buffer_rsrc_t out_rs = block_rsrc(a, wo, wo <= nwin - 1);
-            __amdgpu_buffer_rsrc_t qrs[NB];
+            // 2. Descriptors of the super-step (blocks outside 0 .. nwin-1
+            // are empty; block nwin-1 may be partial).
+            const __amdgpu_buffer_rsrc_t in_rs = make_rsrc(in_base, (uint32_t)in_v < (uint32_t)(nwin - 1) ? full_bytes
+                                                                    : in_v == nwin - 1 ? last_bytes : 0u);
+            const __amdgpu_buffer_rsrc_t out_rs = make_rsrc(out_base, (uint32_t)out_v < (uint32_t)(nwin - 1) ? full_bytes
+                                                                      : out_v == nwin - 1 ? last_bytes : 0u);
+            in_v += 1;
+            out_v += 1;
+            in_base += blk_bytes;
+            out_base += blk_bytes;
+            int qsoff[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                const int wq = sp + 2 - 2 * i;  // band i's window three super-steps on
-                const bool ok = has_bands && wq >= -1 && wq <= nwin - 1;
-                qrs[i] = make_rsrc(qband0 + ((uint64_t)i * (nwin + 1) + (uint64_t)(ok ? wq + 1 : 0)) * kQBytes,
-                                   ok ? (uint32_t)kQBytes : 0u);
+                int wq = sp + 2 - 2 * i;  // band i's window three super-steps on
+                wq = wq < -2 ? -2 : (wq > nwin ? nwin : wq);
+                qsoff[i] = uniform((i * qwin + wq + 2) * kQBytes);
             }
             // 3. LDS before the products: the first band's input block sp,
             // the block to store, and the stage of input block tt+1.
@@ -307,7 +319,7 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
                 } else if (k >= Ops::kQ && k < Ops::kStore) {
                     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
                     const int i = (k - Ops::kQ) >> 1, h = (k - Ops::kQ) & 1;
-                    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(qrs[i], qvoff + 16 * h, 0, kPolicyL2);
+                    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(qrs, qvoff + 16 * h, qsoff[i], kPolicyL2);
                     Qr[(u + 3) & 3][i][2 * h] = __builtin_bit_cast(double, (unsigned long long)q.x | ((unsigned long long)q.y << 32));
                     Qr[(u + 3) & 3][i][2 * h + 1] = __builtin_bit_cast(double, (unsigned long long)q.z | ((unsigned long long)q.w << 32));
                 } else if (k >= Ops::kStore && k < Ops::kStore + 2 * kS) {
@@ -359,10 +371,9 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
             // super-steps ago.
             compiler_fence();
             {
-                const int wp = t + u - off_out - Geom::kPubOff;
-                const bool pub = publish && wv == 0 && wp >= 0 && wp <= nwin - 1;
-                __builtin_amdgcn_raw_buffer_store_b32((unsigned)(wp + 1), make_rsrc((uint64_t)flag_out, pub ? 4u : 0u),
+                __builtin_amdgcn_raw_buffer_store_b32((unsigned)(wp + 1), (uint32_t)wp < (uint32_t)nwin ? flag_on : flag_off,
                                                       0, 0, kPolicyDevice);
+                ++wp;
                 if (publish)
                     wait_vmem_at_most<Ops::kAfterStores>();
             }
@@ -388,19 +399,22 @@ __global__ __launch_bounds__(64) void mfma_prep_q(const T *__restrict__ C, int64
                             int n, int64_t k, int nbands, int nwin, double *__restrict__ q)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)nbands * (nwin + 1) * kWin;
+    const int64_t total = (int64_t)nbands * (nwin + 3) * kWin;
     if (idx >= total)
         return;
     const int row = (int)(idx % kWin);
     const int64_t bw = idx / kWin;
-    const int wi = (int)(bw % (nwin + 1));
-    const int64_t band = bw / (nwin + 1);
-    const int w = wi - 1;
+    const int wi = (int)(bw % (nwin + 3));
+    const int64_t band = bw / (nwin + 3);
+    const int w = wi - 2;
+    // windows -2 and nwin are zero (the sweep's state before a band's first
+    // window and what it passes on after its last)
+    const bool real = w >= -1 && w <= nwin - 1;
     double v[kWin];
 #pragma unroll
     for (int c = 0; c < kWin; ++c)
-        v[c] = c == row ? 1.0 : 0.0;
-    {
+        v[c] = c == row && real ? 1.0 : 0.0;
+    if (real) {
 #pragma unroll
         for (int tau = 0; tau < kSeq; ++tau) {
 #pragma unroll
@@ -504,7 +518,7 @@ hipError_t mfma_occupancy(int nb_wave, int rows, size_t lds, int *blocks)
 hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t st)
 {
     const int nbands = p.mfma_nchunks * p.mfma_nb;
-    const int64_t total = (int64_t)nbands * (p.mfma_nwin + 1) * kWin;
+    const int64_t total = (int64_t)nbands * (p.mfma_nwin + 3) * kWin;
     constexpr int B = 64;
     const unsigned blocks = (unsigned)((total + B - 1) / B);
     double *q = (double *)((char *)ws + p.off_coef);
