@@ -391,24 +391,44 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
         record_timeout(a.status, timed_out);
 }
 
-// Window matrices: thread (band, window w, row r) builds row r of Q(band, w)
-// by applying the window's rotations, in wavefront order, to e_r, then
-// scatters it to the operand layout: lane l, slab s holds Q[4s + l/16][l%16].
+// Window matrices: a block of 64 threads builds 4 consecutive windows of
+// one band (thread 16*wl + r: row r of window wl).  The block first stages
+// the 256 (c, s) pairs its windows use in LDS, loaded coalesced (sequence
+// q, columns 8*w0+7-q .. 8*w0+38-q), identity pairs outside the problem;
+// then every thread applies its window's rotations, in wavefront order, to
+// e_r (reading the pairs as LDS broadcasts) and scatters the row to the
+// operand layout: lane l, slab s holds Q[4s + l/16][l%16].  Windows -2 and
+// nwin are zero.
+constexpr int kPrepWins = 4;  // windows per block
+
 template <typename T>
 __global__ __launch_bounds__(64) void mfma_prep_q(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S, int64_t lds,
                             int n, int64_t k, int nbands, int nwin, double *__restrict__ q)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)nbands * (nwin + 3) * kWin;
-    if (idx >= total)
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    __shared__ f64x2 cs[kSeq][kPrepWins * kSeq];  // [q][column - (8*w0 + 7 - q)]
+    const int qwin = nwin + 3;
+    const int per_band = (qwin + kPrepWins - 1) / kPrepWins;
+    const int64_t band = blockIdx.x / per_band;
+    const int wi0 = (int)(blockIdx.x - band * per_band) * kPrepWins;  // first window index (w = wi - 2)
+    const int tid = (int)threadIdx.x;
+#pragma unroll
+    for (int x = 0; x < kSeq * kPrepWins * kSeq / 64; ++x) {
+        const int e = tid + 64 * x;
+        const int qq = e / (kPrepWins * kSeq), jj = e % (kPrepWins * kSeq);
+        const int64_t j = (int64_t)kSeq * (wi0 - 2) + kSeq - 1 - qq + jj;
+        const int64_t pp = band * kSeq + qq;
+        const bool ok = j >= 0 && j <= n - 2 && pp < k;
+        const int64_t jc = ok ? j : 0, pc = ok ? pp : 0;
+        const double cl = (double)C[jc + pc * ldc], sl = (double)S[jc + pc * lds];
+        cs[qq][jj] = ok ? f64x2{cl, sl} : f64x2{1.0, 0.0};
+    }
+    __syncthreads();
+    const int wl = tid >> 4, row = tid & 15;
+    const int wi = wi0 + wl;
+    if (wi >= qwin)
         return;
-    const int row = (int)(idx % kWin);
-    const int64_t bw = idx / kWin;
-    const int wi = (int)(bw % (nwin + 3));
-    const int64_t band = bw / (nwin + 3);
     const int w = wi - 2;
-    // windows -2 and nwin are zero (the sweep's state before a band's first
-    // window and what it passes on after its last)
     const bool real = w >= -1 && w <= nwin - 1;
     double v[kWin];
 #pragma unroll
@@ -419,23 +439,18 @@ __global__ __launch_bounds__(64) void mfma_prep_q(const T *__restrict__ C, int64
         for (int tau = 0; tau < kSeq; ++tau) {
 #pragma unroll
             for (int qq = 0; qq < kSeq; ++qq) {
-                const int64_t j = (int64_t)kSeq * w + kSeq - 1 + tau - qq;
-                const int64_t pp = band * kSeq + qq;
-                double c = 1.0, s = 0.0;
-                if (j >= 0 && j <= n - 2 && pp < k) {
-                    c = (double)C[j + pp * ldc];
-                    s = (double)S[j + pp * lds];
-                }
-                const int uu = kSeq - 1 + tau - qq;  // j - 8w, compile-time
-
+                // rotation (j, 8*band + qq) with j = 8w + 7 + tau - qq, on
+                // window columns uu = j - 8w and uu + 1
+                const f64x2 p = cs[qq][kSeq * wl + tau];
+                const int uu = kSeq - 1 + tau - qq;
                 const double x = v[uu], y = v[uu + 1];
-                v[uu] = __builtin_fma(c, x, s * y);
-                v[uu + 1] = __builtin_fma(c, y, -(s * x));
+                v[uu] = __builtin_fma(p.x, x, p.y * y);
+                v[uu + 1] = __builtin_fma(p.x, y, -(p.y * x));
             }
         }
     }
     const int s = row >> 2, gg = row & 3;
-    double *dst = q + (bw * 64 + 16 * gg) * 4 + s;
+    double *dst = q + (((int64_t)band * qwin + wi) * 64 + 16 * gg) * 4 + s;
 #pragma unroll
     for (int c = 0; c < kWin; ++c)
         dst[c * 4] = v[c];
@@ -518,16 +533,16 @@ hipError_t mfma_occupancy(int nb_wave, int rows, size_t lds, int *blocks)
 hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t st)
 {
     const int nbands = p.mfma_nchunks * p.mfma_nb;
-    const int64_t total = (int64_t)nbands * (p.mfma_nwin + 3) * kWin;
-    constexpr int B = 64;
-    const unsigned blocks = (unsigned)((total + B - 1) / B);
+    const int64_t blocks = (int64_t)nbands * ((p.mfma_nwin + 3 + kPrepWins - 1) / kPrepWins);
+    if (blocks > INT32_MAX)
+        return hipErrorInvalidConfiguration;
     double *q = (double *)((char *)ws + p.off_coef);
     if (p.esize == 8)
-        mfma_prep_q<double><<<blocks, B, 0, st>>>((const double *)C, p.ldc, (const double *)S, p.lds,
-                                                  (int)p.n, p.k, nbands, p.mfma_nwin, q);
+        mfma_prep_q<double><<<(unsigned)blocks, 64, 0, st>>>((const double *)C, p.ldc, (const double *)S, p.lds,
+                                                             (int)p.n, p.k, nbands, p.mfma_nwin, q);
     else
-        mfma_prep_q<float><<<blocks, B, 0, st>>>((const float *)C, p.ldc, (const float *)S, p.lds,
-                                                 (int)p.n, p.k, nbands, p.mfma_nwin, q);
+        mfma_prep_q<float><<<(unsigned)blocks, 64, 0, st>>>((const float *)C, p.ldc, (const float *)S, p.lds,
+                                                            (int)p.n, p.k, nbands, p.mfma_nwin, q);
     const int64_t words = (int64_t)p.mfma_tiles * p.mfma_nseg * kMfmaFlagStride;
     return launch_zero((int *)((char *)ws + p.off_flags), words, st);
 }
