@@ -52,6 +52,8 @@ DEFAULT = "plain-f64-10240-k192"
 
 
 SWEEP_SOURCES = ("rotseq_chain.hip", "rotseq_device.h", "rotseq_internal.h")
+# sources of each sweep kernel, by the kernel id of rotseq_launch_info
+KERNEL_SOURCES = {2: SWEEP_SOURCES, 3: ("rotseq_mfma.hip", "rotseq_device.h", "rotseq_internal.h")}
 
 
 def _code_only(text):
@@ -72,16 +74,33 @@ def kernel_source_hash(sources=SWEEP_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, launch_bytes_alg):
+def sweep_tag(launch):
+    """Name of the sweep kernel a launch runs (rotseq_launch_info)."""
+    if launch is None:
+        return None
+    if launch.get("kernel") == 3:
+        return f"sweep_mfma<{launch['bands_per_wave']}, {launch['rows_per_wave'] // 16}>"
+    if launch.get("kernel") == 2:
+        return "sweep_chain"
+    return "sweep_multipass"
+
+
+def measured_traffic(workload, launch_bytes_alg, tag=None):
     """HBM bytes per sweep launch from the committed counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the kernel this launch runs (`tag`, when given) and on
+    its current sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
-            rec = json.load(f).get(workload)
+            recs = json.load(f)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_hash") != kernel_source_hash(rec.get("sources", SWEEP_SOURCES)):
+    # a record per workload and kernel ("<workload>/<kernel>"), or per workload
+    rec = recs.get(f"{workload}/{tag}") if tag is not None else None
+    rec = rec or recs.get(workload)
+    if not rec or (tag is not None and rec.get("tag", "sweep_chain") != tag):
+        return None
+    if rec.get("source_hash") != kernel_source_hash(rec.get("sources", SWEEP_SOURCES)):
         return None
     return rec.get("bytes_per_launch", rec.get("bytes_per_call"))
 
@@ -486,6 +505,8 @@ def main():
     ap.add_argument("--k-per-sweep", action="store_true",
                     help="served workload: draw k for every sweep instead of once per request")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", choices=("auto", "chain", "mfma"), default="auto",
+                    help="sweep kernel of the plain workloads (default: the library's choice)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="only summarise the rocprofv3 kernel traces under DIR (no GPU)")
@@ -546,7 +567,9 @@ def main():
     if variant == "refl3":
         step = lambda: rs.refl3seq(A, TAU, NU1, NU2)  # noqa: E731
     elif variant == "right":
-        step = lambda: rs.rotseq(A, C, S)  # noqa: E731
+        kopts = {"auto": None, "chain": {"kernel": rs.KERNEL_CHAIN},
+                 "mfma": {"kernel": rs.KERNEL_MFMA}}[args.kernel]
+        step = lambda: rs.rotseq(A, C, S, opts=kopts)  # noqa: E731
     elif variant == "left":
         step = lambda: rs.rotseq(A, C, S, opts={"left": 1})  # noqa: E731
     else:
@@ -570,10 +593,15 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     gflops = flops / (ms_step * 1e-3) / 1e9
     sweep_ms = prof["sweep_ms"] / max(prof["calls"], 1)
-    traffic = measured_traffic(args.workload, alg_bytes)
-    # Roofline of the sweep: the larger of its compute time at the vector
-    # peak and its compulsory HBM time (A read and written once, the
-    # coefficients read once) decides the bound.
+    launch = None
+    if variant == "right":
+        launch = rs.launch_describe("d" if dtype == "f64" else "s", m, n, k, opts=kopts)
+    tag = sweep_tag(launch)
+    traffic = measured_traffic(args.workload, alg_bytes, tag)
+    # Roofline of the sweep: the larger of its compute time at the FP64
+    # peak (78.6 TFLOP/s for vector and matrix instructions alike) and its
+    # compulsory HBM time (A read and written once, the coefficients read
+    # once) decides the bound.
     t_alu = flops / (PEAK_TFLOPS[dtype] * 1e12) * 1e3
     t_hbm = alg_bytes / (HBM_GBS * 1e9) * 1e3
     if t_hbm > t_alu:
@@ -610,7 +638,7 @@ def main():
             "unit": unit,
             "frac": round(achieved / peak, 4),
             "traffic": traffic,
-            "kernel": "sweep",
+            "kernel": tag or "sweep",
             "kernel_ms": round(sweep_ms, 4),
             "kernel_ms_min": round(prof["sweep_ms_min"], 4),
             "prep_ms": round(prof["prep_ms"] / max(prof["calls"], 1), 4),

@@ -199,12 +199,18 @@ namespace {
 // Launch shape of the matrix-instruction sweep with the smallest modelled
 // time; fills the mfma_* fields, waves, nwg, lds_bytes and remap of `p`
 // and returns the modelled time in seconds (or a negative value if no
-// shape fits).  Model: every SIMD issues one 16x16x4 FP64 product every
-// 64 cycles at 2.35 GHz; a workgroup runs its super-steps (barriers
-// included) one after another, each kMfmaEff slower than its products
-// alone (the other instructions of a super-step do not overlap the FP64
-// matrix pipeline; measured at m = n = 10240, k = 192).
-constexpr double kMfmaEff = 0.75;
+// shape fits).  Model, fitted to measured sweeps of 11 problem sizes and 7
+// shapes (m x n from 512^2 to 32768 x 4096, k from 1 to 192): a workgroup
+// runs T super-steps one after another; in each, a SIMD issues the 16x16x4
+// FP64 products of its resident waves (64 cycles each; 15% slower with one
+// wave per SIMD, whose other instructions then never overlap them) plus
+// about 600 cycles of everything else, 150 more per extra wave; 2.4 GHz;
+// rounds of workgroups follow one another; 15 us of preparation and launch.
+double mfma_step_cycles(int64_t simd_waves, int nb, int rows)
+{
+    const double mfma = (double)simd_waves * nb * rows * 4 * 64 * (simd_waves == 1 ? 1.15 : 1.0);
+    return mfma + 600.0 + 150.0 * (double)(simd_waves - 1);
+}
 
 double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
 {
@@ -242,8 +248,8 @@ double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
             const int64_t simd_waves = (resident * w + 4 * (int64_t)d.cus - 1) / (4 * (int64_t)d.cus);
             const int delay = mfma_seg_delay(nb);
             const int64_t T = 4 + (nseg - 1) * delay + (w - 1) * mfma_wave_stride(nb) + 2 * nb + nwin;
-            const double cycles = (double)rounds * (double)simd_waves * (double)T * nb * rows * 4 * 64;
-            const double t = cycles / 2.35e9 / kMfmaEff;
+            const double cycles = (double)rounds * (double)T * mfma_step_cycles(simd_waves, nb, rows);
+            const double t = cycles / 2.4e9 + 15e-6;
             if (best < 0.0 || t < best * 0.999) {
                 best = t;
                 keep = p;
@@ -266,12 +272,19 @@ double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
     return best;
 }
 
-// Modelled time of the vector chain sweep: its measured rate on large
-// problems (about 44 TFLOP/s counted) with a floor for small ones.
+// Modelled time of the vector chain sweep, fitted to the same measurements:
+// the slower of its arithmetic (about 44 TFLOP/s counted) and its
+// wavefront latency (a tile's waves step through n + k columns at about
+// 0.11 us each), plus 30% of one read and write of A (about 4.5 TB/s;
+// 3.2 TB/s with a single band, whose few waves keep fewer bytes in
+// flight) that does not overlap them, plus 20 us.
 double model_chain(const Plan &p)
 {
     const double flops = 6.0 * (double)p.m * (double)(p.n - 1) * (double)p.k;
-    return flops / 44e12 + 20e-6;
+    const double lat = (double)(p.n + p.k) * 0.11e-6;
+    const double bytes = 2.0 * (double)p.m * (double)p.n * (double)p.esize;
+    const double mem = bytes / (p.k <= 4 ? 3.2e12 : 4.5e12);
+    return std::max(flops / 44e12, lat) + 0.3 * mem + 20e-6;
 }
 
 }  // namespace
