@@ -65,9 +65,17 @@ struct ChainGeom {
     // newest store, and a group needs G + D_glob columns ahead, so the reader
     // trails by about 14 groups; 2 more cover the flag's latency.
     static constexpr int DG = 16;
+    // Streaming launches (every workgroup holds whole chains, so nothing is
+    // handed on through A; small k, where HBM bounds the sweep): the waves
+    // that read or write A run their step loop over H_deep blocks of U steps,
+    // and an A-fed wave's ring holds R_deep columns, twice as many loads in
+    // flight.  (The DPP broadcasts tie a block to 16 steps.)
+    static constexpr int H_deep = 2;
+    static constexpr int R_deep = 32;
     static_assert(K == 4 || K == 6 || K == 8, "band widths of the chain kernel");
     static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0 && U % G == 0,
                   "geometry");
+    static_assert((U * H_deep) % R_deep == 0, "streaming geometry");
 };
 
 struct ChainArgs {
@@ -151,34 +159,34 @@ __device__ __forceinline__ void rotate_bcast_pair(float &x, float &y, double pai
 // keeps the compiler from padding every FMA pair with wait states (it must
 // assume any asm operand may be a DPP source); inside the block the only
 // DPP sources are `a` and `b`, written by the coefficient load, and plain
-// VALU dependencies are interlocked by the hardware.  Operands: %0..%8 the
-// columns, %9 = a, %10 = b, %11.. the broadcast lanes OFF+q.
-#define ROTSEQ_FMAC(X, A, Y, L) "v_fmac_f64_dpp %" #X ", %" #A ", %" #Y " row_newbcast:%" #L " row_mask:0xf bank_mask:0xf\n"
-#define ROTSEQ_ROT(L, X, Y) ROTSEQ_FMAC(X, 9, Y, L) ROTSEQ_FMAC(Y, 10, X, L) ROTSEQ_FMAC(X, 9, Y, L)
-#define ROTSEQ_COLS "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]), "+v"(c[7]), "+v"(c[8])
+// VALU dependencies are interlocked by the hardware.  Operands: %0..%K the
+// columns c[0..K] (only these: a further operand would have to be
+// materialised every step), %[a], %[b], and the broadcast lanes %[lq].
+#define ROTSEQ_FMAC(X, A, Y, L) "v_fmac_f64_dpp %" #X ", %[" #A "], %" #Y " row_newbcast:%[" #L "] row_mask:0xf bank_mask:0xf\n"
+#define ROTSEQ_ROT(L, X, Y) ROTSEQ_FMAC(X, a, Y, L) ROTSEQ_FMAC(Y, b, X, L) ROTSEQ_FMAC(X, a, Y, L)
+#define ROTSEQ_COEF(OFF) [a] "v"(a), [b] "v"(b), [l0] "n"(OFF), [l1] "n"(OFF + 1), [l2] "n"(OFF + 2), [l3] "n"(OFF + 3)
 template <int K, int OFF>
-__device__ __forceinline__ void lift_step(double (&c)[9], double a, double b)
+__device__ __forceinline__ void lift_step(double (&c)[K + 1], double a, double b)
 {
     static_assert(OFF + K <= 16, "broadcast lanes lie in one 16-lane row");
     if constexpr (K == 8)
-        asm(ROTSEQ_ROT(11, 1, 0) ROTSEQ_ROT(12, 2, 1) ROTSEQ_ROT(13, 3, 2) ROTSEQ_ROT(14, 4, 3)
-            ROTSEQ_ROT(15, 5, 4) ROTSEQ_ROT(16, 6, 5) ROTSEQ_ROT(17, 7, 6) ROTSEQ_ROT(18, 8, 7)
-            : ROTSEQ_COLS
-            : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3), "n"(OFF + 4),
-              "n"(OFF + 5), "n"(OFF + 6), "n"(OFF + 7));
+        asm(ROTSEQ_ROT(l0, 1, 0) ROTSEQ_ROT(l1, 2, 1) ROTSEQ_ROT(l2, 3, 2) ROTSEQ_ROT(l3, 4, 3)
+            ROTSEQ_ROT(l4, 5, 4) ROTSEQ_ROT(l5, 6, 5) ROTSEQ_ROT(l6, 7, 6) ROTSEQ_ROT(l7, 8, 7)
+            : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6]),
+              "+v"(c[7]), "+v"(c[8])
+            : ROTSEQ_COEF(OFF), [l4] "n"(OFF + 4), [l5] "n"(OFF + 5), [l6] "n"(OFF + 6),
+              [l7] "n"(OFF + 7));
     else if constexpr (K == 6)
-        asm(ROTSEQ_ROT(11, 1, 0) ROTSEQ_ROT(12, 2, 1) ROTSEQ_ROT(13, 3, 2) ROTSEQ_ROT(14, 4, 3)
-            ROTSEQ_ROT(15, 5, 4) ROTSEQ_ROT(16, 6, 5)
-            : ROTSEQ_COLS
-            : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3), "n"(OFF + 4),
-              "n"(OFF + 5));
+        asm(ROTSEQ_ROT(l0, 1, 0) ROTSEQ_ROT(l1, 2, 1) ROTSEQ_ROT(l2, 3, 2) ROTSEQ_ROT(l3, 4, 3)
+            ROTSEQ_ROT(l4, 5, 4) ROTSEQ_ROT(l5, 6, 5)
+            : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6])
+            : ROTSEQ_COEF(OFF), [l4] "n"(OFF + 4), [l5] "n"(OFF + 5));
     else
-        asm(ROTSEQ_ROT(11, 1, 0) ROTSEQ_ROT(12, 2, 1) ROTSEQ_ROT(13, 3, 2) ROTSEQ_ROT(14, 4, 3)
-            : ROTSEQ_COLS
-            : "v"(a), "v"(b), "n"(OFF), "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3));
+        asm(ROTSEQ_ROT(l0, 1, 0) ROTSEQ_ROT(l1, 2, 1) ROTSEQ_ROT(l2, 3, 2) ROTSEQ_ROT(l3, 4, 3)
+            : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4])
+            : ROTSEQ_COEF(OFF));
 }
-#undef ROTSEQ_COLS
-
+#undef ROTSEQ_COEF
 #undef ROTSEQ_ROT
 #undef ROTSEQ_FMAC
 
@@ -237,7 +245,8 @@ struct CoefLane<float> {
 enum In : int { kInLds = 0, kInFresh = 1, kInWait = 2 };       // LDS channel / A (band 0) / A after a flag
 enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel / A + flag / A (last band)
 
-// One band-wave, unrolled over U steps.
+// One band-wave, unrolled over U steps (H blocks of U steps for the A
+// streams of a streaming launch, DEEP).
 //
 // Flow control inside a workgroup is lockstep: the step loop is cut into
 // groups of G steps, and every wave of the workgroup ends every group at the
@@ -258,7 +267,7 @@ enum Out : int { kOutLds = 0, kOutPublish = 1, kOutFinal = 2 };  // LDS channel 
 // travel as data too (zeros, or past n possibly an older finite column of
 // the same row, which only ever meets identity rotations), and A is
 // protected by empty buffer descriptors.
-template <typename T, int K, int ARITH, int IN, int OUT>
+template <typename T, int K, int ARITH, int IN, int OUT, bool DEEP>
 __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, int w, int pre, int post,
                                          char *lds_generic)
 {
@@ -266,8 +275,10 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     constexpr int U = Geo::U;
     constexpr int RB = Geo::RB;
     constexpr int G = Geo::G;
-    constexpr int R = IN == kInLds ? Geo::R_lds : Geo::R_glob;
+    constexpr int R = IN == kInLds ? Geo::R_lds : DEEP ? Geo::R_deep : Geo::R_glob;
     constexpr int D = R - K - 1;
+    constexpr int H = DEEP && (IN != kInLds || OUT != kOutLds) ? Geo::H_deep : 1;
+    constexpr int UH = U * H;  // steps per trip of the step loop
     constexpr int SLOT = kWave;  // elements per ring slot
     static_assert(U % G == 0, "groups must tile the unroll");
     typedef __attribute__((address_space(3))) T lds_T;
@@ -389,12 +400,12 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         svoff += U * (int)sizeof(T);
     }
     int blk = 0;
-    // Column t-K+1 (step uu of the block) has seen the whole band: to the
+    // Column t-K+1 (ring position hu, step uu of its block of U) has seen the whole band: to the
     // next band's LDS ring, or to A (with its final sign in the last band).
-    auto emit = [&](int uu) {
-        T val = ring[(uu - K + 1 + U) % R];
+    auto emit = [&](int hu, int uu) {
+        T val = ring[(hu - K + 1 + UH) % R];
         if constexpr (OUT == kOutLds) {
-            ring_out[((uu - K + 1 + U) % RB) * SLOT] = val;
+            ring_out[((hu - K + 1 + UH) % RB) * SLOT] = val;
         } else {
             const int c = sc + (uu % G);
             const bool valid = (unsigned)c < (unsigned)n;
@@ -421,9 +432,12 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     // of each group instead of only for the one whose data is used.
     wait_vmem_at_most<0>();
 
-    for (int t0 = 0; t0 < a.steps; t0 += U) {
+    for (int t0 = 0; t0 < a.steps; t0 += UH) {
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            const int hu = h * U + u;  // ring position; u: step within the block
             if constexpr (IN == kInWait) {
                 if (u % G == 0) {
                     // Fold in the flag read a group ago, make sure this group's
@@ -442,32 +456,32 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                 cf[(u / SPL) % NL] = CL::load(crs, cvoff, coff + (u + kAhead) * kStepBytes);
             }
             // Column t+1+D replaces column t-K, finished last step.
-            fetch(ring[(u + D + 1) % R], (u + D + 1) % RB);
+            fetch(ring[(hu + D + 1) % R], (hu + D + 1) % RB);
             select_const<SPL>(u % SPL, [&](auto jc) {
                 constexpr int OFF = decltype(jc)::value * K;
                 if constexpr (sizeof(T) == 8 && ARITH == kLift) {
-                    // c[j] = column t+1-j, j = 0..K (unused operands are dummies).
-                    double c[9];
+                    // c[j] = column t+1-j, j = 0..K.
+                    double c[K + 1];
 #pragma unroll
-                    for (int j = 0; j < 9; ++j)
-                        c[j] = j <= K ? ring[(u + 1 - j + U) % R] : 0.0;
+                    for (int j = 0; j <= K; ++j)
+                        c[j] = ring[(hu + 1 - j + UH) % R];
                     lift_step<K, OFF>(c, CL::a(cur), CL::b(cur));
 #pragma unroll
                     for (int j = 0; j <= K; ++j)
-                        ring[(u + 1 - j + U) % R] = c[j];
+                        ring[(hu + 1 - j + UH) % R] = c[j];
                 } else {
                     static_for<0, K>([&](auto qc) {
                         constexpr int q = decltype(qc)::value;
                         if constexpr (sizeof(T) == 8)
-                            rotate_bcast<ARITH, OFF + q>(ring[(u - q + U) % R], ring[(u - q + 1 + U) % R],
+                            rotate_bcast<ARITH, OFF + q>(ring[(hu - q + UH) % R], ring[(hu - q + 1 + UH) % R],
                                                          CL::a(cur), CL::b(cur));
                         else
-                            rotate_bcast_pair<ARITH, OFF + q>(ring[(u - q + U) % R],
-                                                              ring[(u - q + 1 + U) % R], CL::pair(cur));
+                            rotate_bcast_pair<ARITH, OFF + q>(ring[(hu - q + UH) % R],
+                                                              ring[(hu - q + 1 + UH) % R], CL::pair(cur));
                     });
                 }
             });
-            emit(u);
+            emit(hu, u);
             if (u % G == G - 1) {
                 sc += G;
                 opaque_i(lc);
@@ -493,6 +507,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+      }
     }
     if constexpr (OUT == kOutPublish) {
         wait_vmem_at_most<0>();
@@ -504,16 +519,16 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
         record_timeout(a.status, timed_out);
 }
 
-template <typename T, int K, int ARITH, int IN>
+template <typename T, int K, int ARITH, int IN, bool DEEP>
 __device__ __forceinline__ void bandwave_out(const ChainArgs &a, int tile, int b, int w, int pre,
                                              int post, char *lds, int out)
 {
     if (out == kOutLds)
-        bandwave<T, K, ARITH, IN, kOutLds>(a, tile, b, w, pre, post, lds);
+        bandwave<T, K, ARITH, IN, kOutLds, DEEP>(a, tile, b, w, pre, post, lds);
     else if (out == kOutPublish)
-        bandwave<T, K, ARITH, IN, kOutPublish>(a, tile, b, w, pre, post, lds);
+        bandwave<T, K, ARITH, IN, kOutPublish, DEEP>(a, tile, b, w, pre, post, lds);
     else
-        bandwave<T, K, ARITH, IN, kOutFinal>(a, tile, b, w, pre, post, lds);
+        bandwave<T, K, ARITH, IN, kOutFinal, DEEP>(a, tile, b, w, pre, post, lds);
 }
 
 // Groups by which a chain segment that starts at band b0 is held back in its
@@ -535,8 +550,10 @@ __device__ __forceinline__ int segment_offset(int b0, int W)
 }
 
 // Workgroup g of a problem's chain grid: its waves take the (tile, band)
-// units g*W .. g*W+W-1 in tile-major order.
-template <typename T, int K, int ARITH>
+// units g*W .. g*W+W-1 in tile-major order.  DEEP: a streaming launch, in
+// which W is a multiple of the band count, so that no unit reads or writes
+// a hand-off through A.
+template <typename T, int K, int ARITH, bool DEEP>
 __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char *lds)
 {
     constexpr int LG = ChainGeom<K>::LG;
@@ -571,12 +588,28 @@ __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char 
     const int out = (w + 1 < a.waves && b + 1 < a.nbands) ? kOutLds
                     : (b + 1 < a.nbands ? kOutPublish : kOutFinal);
     const int post = max_pre - pre;
-    if (in == kInLds)
-        bandwave_out<T, K, ARITH, kInLds>(a, tile, b, w, pre, post, lds, out);
-    else if (in == kInFresh)
-        bandwave_out<T, K, ARITH, kInFresh>(a, tile, b, w, pre, post, lds, out);
-    else
-        bandwave_out<T, K, ARITH, kInWait>(a, tile, b, w, pre, post, lds, out);
+    if constexpr (DEEP) {
+        if (in == kInWait || out == kOutPublish) {
+            // A hand-off through A in a streaming launch (the host never
+            // makes one): report the call as a failed hand-off wait and keep
+            // the workgroup's barrier count.
+            if (threadIdx.x % kWave == 0)
+                record_timeout(a.status, kWaitFlag);
+            idle_groups(max_pre + 1 + a.steps / ChainGeom<K>::G);
+            return;
+        }
+        if (in == kInLds)
+            bandwave_out<T, K, ARITH, kInLds, true>(a, tile, b, w, pre, post, lds, out);
+        else
+            bandwave_out<T, K, ARITH, kInFresh, true>(a, tile, b, w, pre, post, lds, out);
+    } else {
+        if (in == kInLds)
+            bandwave_out<T, K, ARITH, kInLds, false>(a, tile, b, w, pre, post, lds, out);
+        else if (in == kInFresh)
+            bandwave_out<T, K, ARITH, kInFresh, false>(a, tile, b, w, pre, post, lds, out);
+        else
+            bandwave_out<T, K, ARITH, kInWait, false>(a, tile, b, w, pre, post, lds, out);
+    }
 }
 
 // Zeroes the workgroup's LDS rings, so that a column slot read before its
@@ -588,14 +621,16 @@ __device__ __forceinline__ void zero_lds(char *lds, uint32_t words)
     __syncthreads();
 }
 
-template <typename T, int K, int ARITH>
-__global__ __launch_bounds__(1024) void sweep_chain(ChainArgs a)
+// DEEP: a streaming launch of at most kChainDeepWaves waves per workgroup
+// (the bound leaves the deeper rings their registers).
+template <typename T, int K, int ARITH, bool DEEP>
+__global__ __launch_bounds__(DEEP ? kChainDeepWaves * kWave : 1024) void sweep_chain(ChainArgs a)
 {
     extern __shared__ __align__(16) char lds[];
     zero_lds(lds, a.lds_words);
     const int p = (int)blockIdx.x;
     const int g = a.remap ? (p & 7) * (a.nwg >> 3) + (p >> 3) : p;
-    chain_workgroup<T, K, ARITH>(a, g, lds);
+    chain_workgroup<T, K, ARITH, DEEP>(a, g, lds);
 }
 
 // A batch in one launch: workgroup ranges of the items follow each other in
@@ -642,7 +677,7 @@ __global__ __launch_bounds__(1024) void sweep_chain_batch(BatchChainArgs ba)
     a.sign = (uint64_t)it.sign;
     a.flags = it.flags;
     a.status = it.status;
-    chain_workgroup<T, K, ARITH>(a, (int)(g - it.off_wg), lds);
+    chain_workgroup<T, K, ARITH, false>(a, (int)(g - it.off_wg), lds);
 }
 
 template <typename T, int K, int ARITH>
@@ -667,7 +702,10 @@ hipError_t go_chain(const Plan &p, T *A, const char *ws, hipStream_t st)
     a.sign = (uint64_t)(ws + p.off_sign);
     a.flags = (int *)(ws + p.off_flags);
     a.status = p.status;
-    sweep_chain<T, K, ARITH><<<p.nwg, p.waves * kWave, p.lds_bytes, st>>>(a);
+    if (p.deep)
+        sweep_chain<T, K, ARITH, true><<<p.nwg, p.waves * kWave, p.lds_bytes, st>>>(a);
+    else
+        sweep_chain<T, K, ARITH, false><<<p.nwg, p.waves * kWave, p.lds_bytes, st>>>(a);
     return hipGetLastError();
 }
 
@@ -731,10 +769,12 @@ hipError_t chain_t(const Plan &p, T *A, const char *ws, hipStream_t st)
 }
 
 template <typename T>
-const void *chain_kernel_fn(int band, int arith, bool batch)
+const void *chain_kernel_fn(int band, int arith, bool batch, bool deep)
 {
-#define ROTSEQ_CHAIN_FN(KK, AA) \
-    (batch ? (const void *)&sweep_chain_batch<T, KK, AA> : (const void *)&sweep_chain<T, KK, AA>)
+#define ROTSEQ_CHAIN_FN(KK, AA)                                                                    \
+    (batch  ? (const void *)&sweep_chain_batch<T, KK, AA>                                          \
+     : deep ? (const void *)&sweep_chain<T, KK, AA, true>                                          \
+            : (const void *)&sweep_chain<T, KK, AA, false>)
     if (band == 4)
         return arith == kExact ? ROTSEQ_CHAIN_FN(4, kExact)
                : arith == kFma ? ROTSEQ_CHAIN_FN(4, kFma)
@@ -751,10 +791,10 @@ const void *chain_kernel_fn(int band, int arith, bool batch)
 
 }  // namespace
 
-int chain_unroll(int band)
+int chain_unroll(int band, bool deep)
 {
     (void)band;
-    return ChainGeom<8>::U;
+    return ChainGeom<8>::U * (deep ? ChainGeom<8>::H_deep : 1);
 }
 
 size_t chain_lds_bytes(int band, int waves, int esize)
@@ -766,10 +806,10 @@ size_t chain_lds_bytes(int band, int waves, int esize)
 }
 
 hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,
-                           bool batch)
+                           bool batch, bool deep)
 {
-    const void *fn = esize == 8 ? chain_kernel_fn<double>(band, arith, batch)
-                                : chain_kernel_fn<float>(band, arith, batch);
+    const void *fn = esize == 8 ? chain_kernel_fn<double>(band, arith, batch, deep)
+                                : chain_kernel_fn<float>(band, arith, batch, deep);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, waves * kWave, lds);
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -52,6 +53,7 @@ bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok)
     // The chain kernel addresses the n column signs with 32-bit byte
     // offsets; past 2^28 columns the multipass kernel takes over.
     constexpr int64_t kChainMaxN = (int64_t)1 << 28;
+    p.deep = 0;
     if (req_kernel == kMfma) {
         // Window matrices for the forward right application of rotations
         // to a column-major FP64 matrix with 32-bit column offsets per block.
@@ -81,15 +83,17 @@ bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok)
     p.mfma_ok = req_kernel == 0 && mfma_ok && p.kernel == kChain ? 1 : 0;
     int band = req_band;
     if (p.kernel == kChain) {
-        // K = 8 by default.  With 4 < k <= 8 a single band of 8 leaves one
-        // wave per row tile; two chained bands of 4 double the waves, which
-        // is what the memory-bound regime of small k needs (32768 x 4096,
-        // k = 8: 0.68 -> 0.49 ms).
+        // K = 8 by default.  With k <= 8 a single band of 8 would leave one
+        // wave per row tile, which reads, rotates and writes every column;
+        // two chained bands of 4 (the second one identity rotations when
+        // k <= 4) split the A reads and writes over two waves, which is
+        // what the memory-bound regime of small k needs (32768 x 4096,
+        // k = 8: 0.68 -> 0.49 ms; k = 1: 0.56 -> 0.40 ms with the
+        // streaming form).
         if (band == 0)
-            band = p.k > 4 && p.k <= 8 ? 4 : 8;
+            band = p.k <= 8 ? 4 : 8;
         if (band != 4 && band != 6 && band != 8)
             return false;
-        p.unroll = chain_unroll(band);
     } else if (p.kernel == kMultipass) {
         if (band == 0) {
             band = 1;
@@ -105,6 +109,11 @@ bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok)
     p.band = band;
     p.pad = p.kernel == kChain ? kChainCoefPad : 1;
     p.npass = (int)((p.k + band - 1) / band);
+    if (p.kernel == kChain) {
+        if (req_band == 0 && p.npass < 2)
+            p.npass = 2;  // bands past the k-th sequence are identity
+        p.unroll = chain_unroll(band, p.npass <= kChainDeepBands);
+    }
     const int64_t real_steps = p.n + band - 1;  // t = 0 .. n+K-2
     p.steps = (int)(((real_steps + p.unroll - 1) / p.unroll) * p.unroll);
     const int64_t n1 = p.n - 1;
@@ -278,13 +287,24 @@ double plan_mfma(Plan &p, int req_waves, int req_shape, const DeviceInfo &d)
 // 0.11 us each), plus 30% of one read and write of A (about 4.5 TB/s;
 // 3.2 TB/s with a single band, whose few waves keep fewer bytes in
 // flight) that does not overlap them, plus 20 us.
-double model_chain(const Plan &p)
+double model_chain(const Plan &p, int cus)
 {
     const double flops = 6.0 * (double)p.m * (double)(p.n - 1) * (double)p.k;
-    const double lat = (double)(p.n + p.k) * 0.11e-6;
     const double bytes = 2.0 * (double)p.m * (double)p.n * (double)p.esize;
-    const double mem = bytes / (p.k <= 4 ? 3.2e12 : 4.5e12);
-    return std::max(flops / 44e12, lat) + 0.3 * mem + 20e-6;
+    if (p.npass <= kChainDeepBands) {
+        // Streaming form: a lone wave's step costs about 78 ns with bands of
+        // 4 and 120 ns with bands of 8 (one wave issues at most one
+        // instruction per 4 cycles); each further wave per SIMD adds 3/4 of
+        // that, unless HBM (about 5 TB/s for this mix of reads and writes)
+        // takes longer.  Fitted to FP64 sweeps of m = 1024 .. 65536,
+        // n = 1024 .. 16384, k = 1 .. 32.
+        const double waves = (double)((p.m + 63) / 64) * (double)p.npass;
+        const double per_simd = std::max(1.0, std::ceil(waves / (4.0 * (double)cus)));
+        const double step = (p.band <= 4 ? 78e-9 : 120e-9) * (1.0 + 0.75 * (per_simd - 1.0));
+        return std::max((double)p.steps * step, bytes / 5.0e12) + 15e-6;
+    }
+    const double lat = (double)(p.n + p.k) * 0.11e-6;
+    return std::max(flops / 44e12, lat) + 0.3 * bytes / 4.5e12 + 20e-6;
 }
 
 }  // namespace
@@ -300,7 +320,7 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
                                             : plan_mfma(trial, 0, 0, d);
         if (p.kernel == kMfma && t < 0.0)
             return hipErrorInvalidConfiguration;
-        if (t >= 0.0 && (p.kernel == kMfma || t < model_chain(p))) {
+        if (t >= 0.0 && (p.kernel == kMfma || t < model_chain(p, d.cus))) {
             p = trial;
             p.kernel = kMfma;
             p.spin_limit = wait_spin_limit();
@@ -320,7 +340,10 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
     // once (registers and LDS), so ceil(nwg / (occ * CUs)) rounds run one
     // after another, and within a round the busiest SIMD holds
     // ceil(W * wgs_per_cu / 4) waves.  Ties go to fewer workgroups (fewer
-    // hand-offs through A).
+    // hand-offs through A).  A chain of at most kChainDeepBands bands runs
+    // in the streaming form, whole in one workgroup: W a multiple of the
+    // band count, at most kChainDeepWaves.
+    const bool stream = p.npass <= kChainDeepBands && p.steps % chain_unroll(p.band, true) == 0;
     int waves = 0, per_cu = 1;
     size_t lds = 0;
     if (req_waves > 0) {
@@ -328,14 +351,20 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
         lds = chain_lds_bytes(p.band, waves, p.esize);
         while (waves > 1 && lds > d.max_lds)
             lds = chain_lds_bytes(p.band, --waves, p.esize);
+        p.deep = stream && waves <= kChainDeepWaves && waves % p.npass == 0 ? 1 : 0;
     } else {
+        p.deep = stream ? 1 : 0;
         double best = 1e300;
         for (int wv = 1; wv <= 16; ++wv) {
+            if (p.deep && (wv > kChainDeepWaves || wv % p.npass != 0))
+                continue;
             const size_t l = chain_lds_bytes(p.band, wv, p.esize);
             if (l > d.max_lds)
                 break;
             int occ = 0;
-            if (chain_occupancy(p.band, p.arith, p.esize, wv, l, &occ) != hipSuccess || occ < 1)
+            if (chain_occupancy(p.band, p.arith, p.esize, wv, l, &occ, false, p.deep != 0) !=
+                    hipSuccess ||
+                occ < 1)
                 continue;
             const int64_t nwg = (total + wv - 1) / wv;
             const int64_t slots = (int64_t)occ * d.cus;
@@ -352,8 +381,8 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
             }
         }
         if (waves == 0) {
-            waves = 1;
-            lds = chain_lds_bytes(p.band, 1, p.esize);
+            waves = p.deep ? p.npass : 1;
+            lds = chain_lds_bytes(p.band, waves, p.esize);
         }
     }
     (void)per_cu;
@@ -361,7 +390,7 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
     p.lds_bytes = lds;
     p.nwg = (int)((total + waves - 1) / waves);
     int occ = 0;
-    hipError_t e = chain_occupancy(p.band, p.arith, p.esize, waves, lds, &occ);
+    hipError_t e = chain_occupancy(p.band, p.arith, p.esize, waves, lds, &occ, false, p.deep != 0);
     if (e != hipSuccess)
         return e;
     // Consecutive workgroups share tiles; placing them on one XCD keeps the

@@ -50,6 +50,7 @@ struct Plan {
     int esize;   // sizeof element: 8 (double) or 4 (float)
     // Launch shape of the chain kernel (configure_launch).
     int waves, nwg, remap, publish, spin_limit, wait_bias;
+    int deep;  // streaming form: whole chains per workgroup (chain_unroll(band, true))
     size_t lds_bytes;
     int *status;  // sticky device error word (ROTSEQ_E_* bits)
     // Matrix-instruction sweep (kMfma): bands per wave, 16-row blocks per
@@ -142,10 +143,16 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
 
 // Register-ring length (= unroll length) of the sweep kernels for a band.
 int unroll_for_band(int band);
-int chain_unroll(int band);
+// Step unroll of the chain kernel; `deep`: its streaming form, which launches
+// whose bands all fit one workgroup use when there are at most
+// kChainDeepBands of them (the memory-bound regime of small k), with at most
+// kChainDeepWaves waves per workgroup.
+constexpr int kChainDeepBands = 4;
+constexpr int kChainDeepWaves = 4;
+int chain_unroll(int band, bool deep);
 size_t chain_lds_bytes(int band, int waves, int esize);
 hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,
-                           bool batch = false);
+                           bool batch = false, bool deep = false);
 hipError_t launch_chain(const Plan &p, void *A, const void *ws, hipStream_t stream);
 
 // Matrix-instruction sweep (rotseq_mfma.hip).
