@@ -169,7 +169,6 @@ hipError_t launch_mfma(const Plan &p, void *A, const void *ws, hipStream_t strea
 // Launchers (rotseq_kernels.hip).  All are asynchronous on `stream` and
 // return the hipError_t of the launch.
 // p[0 .. count) = 0 by a kernel (also under graph capture).
-hipError_t launch_zero(int *p, int64_t count, hipStream_t stream);
 hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws,
                        hipStream_t stream);
 hipError_t launch_sweep(const Plan &p, void *A, const void *ws, hipStream_t stream);

@@ -212,14 +212,20 @@ __device__ __forceinline__ uint64_t negmask_elem(const T *__restrict__ C, int64_
 // parity[pass*(n-1) + j] = parities of the negations by pair j in bands
 // < pass (bit 0: of its left column, bit 1: of its right column), for
 // pass = 0 .. npass (the last row is the total).
+// Parities of one band's negations of a pair (bit 0: its left column,
+// bit 1: its right column).
+__device__ __forceinline__ unsigned negmask_parities(uint64_t nm)
+{
+    return (__builtin_popcount((unsigned)nm) & 1u) | ((__builtin_popcount((unsigned)(nm >> 32)) & 1u) << 1);
+}
+
 __device__ __forceinline__ void parity_elem(const uint64_t *__restrict__ negmask, int64_t n1,
                                             int npass, uint8_t *__restrict__ parity, int64_t j)
 {
     unsigned acc = 0;
     for (int pass = 0; pass < npass; ++pass) {
         parity[(int64_t)pass * n1 + j] = (uint8_t)acc;
-        const uint64_t nm = negmask[(int64_t)pass * n1 + j];
-        acc ^= (__builtin_popcount((unsigned)nm) & 1u) | ((__builtin_popcount((unsigned)(nm >> 32)) & 1u) << 1);
+        acc ^= negmask_parities(negmask[(int64_t)pass * n1 + j]);
     }
     parity[(int64_t)npass * n1 + j] = (uint8_t)acc;
 }
@@ -288,58 +294,54 @@ __device__ __forceinline__ CoefPair<T> coef_elem(const T *__restrict__ C, int64_
     return out;
 }
 
+// Lifting form, first launch: thread j computes pair j's negation masks
+// band by band and, as it goes, their parities over the bands before each
+// one (the last row of `parity` is the total over all bands).
 template <typename T>
-__global__ void prep_negmask(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
-                             int64_t lds, int64_t n1, int64_t k, int K, int npass, int kind,
-                             uint64_t *__restrict__ negmask, int *status)
+__global__ void prep_masks(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
+                           int64_t lds, int64_t n1, int64_t k, int K, int npass, int kind,
+                           uint64_t *__restrict__ negmask, uint8_t *__restrict__ parity, int *status)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)npass * n1)
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n1)
         return;
     bool nonortho = false;
-    negmask[idx] = negmask_elem(C, cj, ldc, S, lds, n1, k, K, kind, idx, nonortho);
+    unsigned acc = 0;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int64_t idx = (int64_t)pass * n1 + j;
+        const uint64_t nm = negmask_elem(C, cj, ldc, S, lds, n1, k, K, kind, idx, nonortho);
+        negmask[idx] = nm;
+        parity[idx] = (uint8_t)acc;
+        acc ^= negmask_parities(nm);
+    }
+    parity[(int64_t)npass * n1 + j] = (uint8_t)acc;
     if (nonortho)
         __hip_atomic_fetch_or(status, ROTSEQ_STATUS_NOT_ORTHOGONAL, __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void prep_parity(const uint64_t *__restrict__ negmask, int64_t n1, int npass,
-                            uint8_t *__restrict__ parity)
-{
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n1)
-        return;
-    parity_elem(negmask, n1, npass, parity, j);
-}
-
-template <typename T>
-__global__ void prep_sign(const uint8_t *__restrict__ total, int64_t n, T *__restrict__ sign)
-{
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n)
-        return;
-    sign[c] = sign_elem<T>(total, n, c);
-}
-
+// Second (or, without the lifting form, only) launch: the coefficient
+// records; threads c < n also write column c's final sign (lifting form,
+// from the total parities of the first launch), and threads i < flag_words
+// zero the sweep's progress flags.
 template <typename T>
 __global__ void prep_coef(const T *__restrict__ C, int64_t cj, int64_t ldc, const T *__restrict__ S,
                           int64_t lds, int64_t n1, int64_t k, int K, int steps, int pad, int npass,
                           int arith, int kind, const uint64_t *__restrict__ negmask,
-                          const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef)
+                          const uint8_t *__restrict__ parity, CoefPair<T> *__restrict__ coef,
+                          T *__restrict__ sign, int *__restrict__ flags, int64_t flag_words)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < flag_words)
+        flags[idx] = 0;
+    if (arith == kLift && idx < n1 + 1)
+        sign[idx] = sign_elem<T>(parity + (int64_t)npass * n1, n1 + 1, idx);
     const int64_t total = (int64_t)npass * (steps + pad) * K;
     if (idx >= total)
         return;
     coef[idx] = coef_elem(C, cj, ldc, S, lds, n1, k, K, steps, pad, arith, kind, negmask, parity, idx);
 }
 
-__global__ void prep_zero(int *__restrict__ p, int64_t count)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count)
-        p[i] = 0;
-}
 
 // ------------------------------------------------------------- packing
 //
@@ -479,20 +481,16 @@ hipError_t prep_t(const Plan &p, const T *C, const T *S, char *ws, hipStream_t s
     T *sign = (T *)(ws + p.off_sign);
     CoefPair<T> *coef = (CoefPair<T> *)(ws + p.off_coef);
     constexpr int B = 256;
-    if (p.arith == kLift) {
-        prep_negmask<T><<<blocks_for((int64_t)p.npass * n1, B), B, 0, st>>>(
-            C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band, p.npass, p.kind, negmask, p.status);
-        prep_parity<<<blocks_for(n1, B), B, 0, st>>>(negmask, n1, p.npass, parity);
-        prep_sign<T><<<blocks_for(p.n, B), B, 0, st>>>(parity + (int64_t)p.npass * n1, p.n, sign);
-    }
+    if (p.arith == kLift)
+        prep_masks<T><<<blocks_for(n1, B), B, 0, st>>>(C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band,
+                                                      p.npass, p.kind, negmask, parity, p.status);
     const int64_t total = (int64_t)p.npass * (p.steps + p.pad) * p.band;
-    if (p.kernel == kChain) {
-        const int64_t words = ((p.m + 63) / 64) * (int64_t)p.npass;
-        prep_zero<<<blocks_for(words, B), B, 0, st>>>((int *)(ws + p.off_flags), words);
-    }
-    prep_coef<T><<<blocks_for(total, B), B, 0, st>>>(C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band,
-                                                    p.steps, p.pad, p.npass, p.arith, p.kind, negmask,
-                                                    parity, coef);
+    const int64_t words = p.kernel == kChain ? ((p.m + 63) / 64) * (int64_t)p.npass : 0;
+    const int64_t threads = std::max(std::max(total, words), p.arith == kLift ? (int64_t)p.n : 0);
+    prep_coef<T><<<blocks_for(threads, B), B, 0, st>>>(C, p.cstep, p.ldc, S, p.lds, n1, p.k, p.band,
+                                                      p.steps, p.pad, p.npass, p.arith, p.kind, negmask,
+                                                      parity, coef, sign, (int *)(ws + p.off_flags),
+                                                      words);
     return hipGetLastError();
 }
 
@@ -557,14 +555,6 @@ hipError_t sweep_t(const Plan &p, T *A, const char *ws, hipStream_t st)
 }  // namespace
 
 int unroll_for_band(int band) { return band + 1 + kPrefetch; }
-
-hipError_t launch_zero(int *p, int64_t count, hipStream_t stream)
-{
-    if (count <= 0)
-        return hipSuccess;
-    prep_zero<<<blocks_for(count, 256), 256, 0, stream>>>(p, count);
-    return hipGetLastError();
-}
 
 hipError_t launch_prep(const Plan &p, const void *C, const void *S, void *ws, hipStream_t stream)
 {

@@ -401,9 +401,12 @@ __global__ __launch_bounds__(kWaves * kWave, 1) void sweep_mfma(MfmaArgs a)
 // nwin are zero.
 constexpr int kPrepWins = 4;  // windows per block
 
+// Also zeroes the sweep's progress flags (flag_words ints), spread over the
+// launch's threads.
 template <typename T>
 __global__ __launch_bounds__(64) void mfma_prep_q(const T *__restrict__ C, int64_t ldc, const T *__restrict__ S, int64_t lds,
-                            int n, int64_t k, int nbands, int nwin, double *__restrict__ q)
+                            int n, int64_t k, int nbands, int nwin, double *__restrict__ q,
+                            int *__restrict__ flags, int64_t flag_words)
 {
     typedef double f64x2 __attribute__((ext_vector_type(2)));
     __shared__ f64x2 cs[kSeq][kPrepWins * kSeq];  // [q][column - (8*w0 + 7 - q)]
@@ -412,6 +415,8 @@ __global__ __launch_bounds__(64) void mfma_prep_q(const T *__restrict__ C, int64
     const int64_t band = blockIdx.x / per_band;
     const int wi0 = (int)(blockIdx.x - band * per_band) * kPrepWins;  // first window index (w = wi - 2)
     const int tid = (int)threadIdx.x;
+    for (int64_t i = (int64_t)blockIdx.x * 64 + tid; i < flag_words; i += (int64_t)gridDim.x * 64)
+        flags[i] = 0;
 #pragma unroll
     for (int x = 0; x < kSeq * kPrepWins * kSeq / 64; ++x) {
         const int e = tid + 64 * x;
@@ -537,14 +542,17 @@ hipError_t launch_mfma_prep(const Plan &p, const void *C, const void *S, void *w
     if (blocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     double *q = (double *)((char *)ws + p.off_coef);
+    int *flags = (int *)((char *)ws + p.off_flags);
+    const int64_t words = (int64_t)p.mfma_tiles * p.mfma_nseg * kMfmaFlagStride;
     if (p.esize == 8)
         mfma_prep_q<double><<<(unsigned)blocks, 64, 0, st>>>((const double *)C, p.ldc, (const double *)S, p.lds,
-                                                             (int)p.n, p.k, nbands, p.mfma_nwin, q);
+                                                             (int)p.n, p.k, nbands, p.mfma_nwin, q, flags,
+                                                             words);
     else
         mfma_prep_q<float><<<(unsigned)blocks, 64, 0, st>>>((const float *)C, p.ldc, (const float *)S, p.lds,
-                                                            (int)p.n, p.k, nbands, p.mfma_nwin, q);
-    const int64_t words = (int64_t)p.mfma_tiles * p.mfma_nseg * kMfmaFlagStride;
-    return launch_zero((int *)((char *)ws + p.off_flags), words, st);
+                                                            (int)p.n, p.k, nbands, p.mfma_nwin, q, flags,
+                                                            words);
+    return hipGetLastError();
 }
 
 hipError_t launch_mfma(const Plan &p, void *A, const void *ws, hipStream_t st)
