@@ -66,16 +66,22 @@ struct ChainGeom {
     // trails by about 14 groups; 2 more cover the flag's latency.
     static constexpr int DG = 16;
     // Streaming launches (every workgroup holds whole chains, so nothing is
-    // handed on through A; small k, where HBM bounds the sweep): the waves
-    // that read or write A run their step loop over H_deep blocks of U steps,
-    // and an A-fed wave's ring holds R_deep columns, twice as many loads in
-    // flight.  (The DPP broadcasts tie a block to 16 steps.)
+    // handed on through A; small k, where HBM bounds the sweep): the step
+    // loop runs over H_deep blocks of U steps, an A-fed wave's ring holds
+    // R_deep columns, twice as many loads in flight, and lockstep groups are
+    // G_deep steps long, half the barriers, with LDS channels of RB_deep
+    // slots and a lag of LG_deep groups (the smallest safe one for those).
+    // (The DPP broadcasts tie a block to 16 steps.)
     static constexpr int H_deep = 2;
     static constexpr int R_deep = 32;
+    static constexpr int G_deep = 8;
+    static constexpr int RB_deep = 32;
+    static constexpr int LG_deep = K == 8 ? 3 : 2;
     static_assert(K == 4 || K == 6 || K == 8, "band widths of the chain kernel");
     static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0 && U % G == 0,
                   "geometry");
-    static_assert((U * H_deep) % R_deep == 0, "streaming geometry");
+    static_assert((U * H_deep) % R_deep == 0 && (U * H_deep) % RB_deep == 0 && U % G_deep == 0,
+                  "streaming geometry");
 };
 
 struct ChainArgs {
@@ -273,11 +279,11 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
 {
     using Geo = ChainGeom<K>;
     constexpr int U = Geo::U;
-    constexpr int RB = Geo::RB;
-    constexpr int G = Geo::G;
+    constexpr int RB = DEEP ? Geo::RB_deep : Geo::RB;
+    constexpr int G = DEEP ? Geo::G_deep : Geo::G;
     constexpr int R = IN == kInLds ? Geo::R_lds : DEEP ? Geo::R_deep : Geo::R_glob;
     constexpr int D = R - K - 1;
-    constexpr int H = DEEP && (IN != kInLds || OUT != kOutLds) ? Geo::H_deep : 1;
+    constexpr int H = DEEP ? Geo::H_deep : 1;
     constexpr int UH = U * H;  // steps per trip of the step loop
     constexpr int SLOT = kWave;  // elements per ring slot
     static_assert(U % G == 0, "groups must tile the unroll");
@@ -556,7 +562,8 @@ __device__ __forceinline__ int segment_offset(int b0, int W)
 template <typename T, int K, int ARITH, bool DEEP>
 __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char *lds)
 {
-    constexpr int LG = ChainGeom<K>::LG;
+    constexpr int LG = DEEP ? ChainGeom<K>::LG_deep : ChainGeom<K>::LG;
+    constexpr int G = DEEP ? ChainGeom<K>::G_deep : ChainGeom<K>::G;
     const int w = uniform((int)(threadIdx.x >> 6));
     const int64_t total = (int64_t)a.tiles * a.nbands;
     // Idle groups before each wave's prologue: its segment's offset plus LG
@@ -579,7 +586,7 @@ __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char 
     const int64_t idx = (int64_t)g * a.waves + w;
     if (idx >= total) {
         // No unit: keep the workgroup's barrier count.
-        idle_groups(max_pre + 1 + a.steps / ChainGeom<K>::G);
+        idle_groups(max_pre + 1 + a.steps / G);
         return;
     }
     const int tile = (int)(idx / a.nbands);
@@ -595,7 +602,7 @@ __device__ __forceinline__ void chain_workgroup(const ChainArgs &a, int g, char 
             // the workgroup's barrier count.
             if (threadIdx.x % kWave == 0)
                 record_timeout(a.status, kWaitFlag);
-            idle_groups(max_pre + 1 + a.steps / ChainGeom<K>::G);
+            idle_groups(max_pre + 1 + a.steps / G);
             return;
         }
         if (in == kInLds)
@@ -797,11 +804,12 @@ int chain_unroll(int band, bool deep)
     return ChainGeom<8>::U * (deep ? ChainGeom<8>::H_deep : 1);
 }
 
-size_t chain_lds_bytes(int band, int waves, int esize)
+size_t chain_lds_bytes(int band, int waves, int esize, bool deep)
 {
     (void)band;
     // at least one word, so that the zeroing loop has a valid extent
-    const size_t rings = (size_t)(waves > 1 ? waves - 1 : 0) * ChainGeom<8>::RB * kWave * esize;
+    const size_t slots = deep ? ChainGeom<8>::RB_deep : ChainGeom<8>::RB;
+    const size_t rings = (size_t)(waves > 1 ? waves - 1 : 0) * slots * kWave * esize;
     return rings > 0 ? rings : 4;
 }
 

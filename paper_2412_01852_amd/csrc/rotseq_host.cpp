@@ -352,13 +352,14 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
         while (waves > 1 && lds > d.max_lds)
             lds = chain_lds_bytes(p.band, --waves, p.esize);
         p.deep = stream && waves <= kChainDeepWaves && waves % p.npass == 0 ? 1 : 0;
+        lds = chain_lds_bytes(p.band, waves, p.esize, p.deep != 0);
     } else {
         p.deep = stream ? 1 : 0;
         double best = 1e300;
         for (int wv = 1; wv <= 16; ++wv) {
             if (p.deep && (wv > kChainDeepWaves || wv % p.npass != 0))
                 continue;
-            const size_t l = chain_lds_bytes(p.band, wv, p.esize);
+            const size_t l = chain_lds_bytes(p.band, wv, p.esize, p.deep != 0);
             if (l > d.max_lds)
                 break;
             int occ = 0;
@@ -382,7 +383,7 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
         }
         if (waves == 0) {
             waves = p.deep ? p.npass : 1;
-            lds = chain_lds_bytes(p.band, waves, p.esize);
+            lds = chain_lds_bytes(p.band, waves, p.esize, p.deep != 0);
         }
     }
     (void)per_cu;

@@ -47,9 +47,10 @@ def kernel_constants():
     return get("U"), get("RB"), get("G")
 
 
-def violations(K, lg, steps):
+def violations(K, lg, steps, G=G, RB=RB):
     """Columns whose slot hand-off is unsafe under lag `lg` (producer at
-    position 0, consumer at position 1)."""
+    position 0, consumer at position 1), with groups of G steps and RB-slot
+    channels."""
     D = geometry(K)
     write = lambda c: 1 + (c + K - 1) // G  # noqa: E731  producer group writing column c
 
@@ -68,6 +69,27 @@ def violations(K, lg, steps):
 
 def test_constants_match_kernel():
     assert kernel_constants() == (U, RB, G)
+
+
+# The streaming form (whole chains per workgroup): longer groups, larger
+# channels, its own lag.
+def deep_constants():
+    src = open(CHAIN).read()
+    get = lambda name: int(re.search(r"static constexpr int %s = (\d+);" % name, src).group(1))  # noqa: E731
+    m = re.search(r"static constexpr int LG_deep = K == 8 \? (\d+) : (\d+);", src)
+    assert m, "LG_deep definition not found in the chain kernel"
+    return get("G_deep"), get("RB_deep"), get("H_deep"), (int(m.group(1)), int(m.group(2)))
+
+
+@pytest.mark.parametrize("K", [4, 6, 8])
+@pytest.mark.parametrize("steps", [32, 64, 4128])
+def test_streaming_lag_is_safe_and_smallest(K, steps):
+    g, rb, h, (lg8, lg) = deep_constants()
+    lag = lg8 if K == 8 else lg
+    assert (U * h) % rb == 0 and U % g == 0
+    assert violations(K, lag, steps, g, rb) == []
+    if steps > 64:
+        assert violations(K, lag - 1, steps, g, rb), "a smaller lag would do"
 
 
 @pytest.mark.parametrize("K", [4, 6, 8])
