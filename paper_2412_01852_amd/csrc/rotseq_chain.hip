@@ -77,7 +77,7 @@ struct ChainGeom {
     static constexpr int G_deep = 8;
     static constexpr int RB_deep = 32;
     static constexpr int LG_deep = K == 8 ? 3 : 2;
-    static_assert(K == 4 || K == 6 || K == 8, "band widths of the chain kernel");
+    static_assert(K == 2 || K == 4 || K == 6 || K == 8, "band widths of the chain kernel");
     static_assert(D_lds >= 1 && U % R_lds == 0 && U % R_glob == 0 && U % RB == 0 && U % G == 0,
                   "geometry");
     static_assert((U * H_deep) % R_deep == 0 && (U * H_deep) % RB_deep == 0 && U % G_deep == 0,
@@ -187,10 +187,14 @@ __device__ __forceinline__ void lift_step(double (&c)[K + 1], double a, double b
             ROTSEQ_ROT(l4, 5, 4) ROTSEQ_ROT(l5, 6, 5)
             : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4]), "+v"(c[5]), "+v"(c[6])
             : ROTSEQ_COEF(OFF), [l4] "n"(OFF + 4), [l5] "n"(OFF + 5));
-    else
+    else if constexpr (K == 4)
         asm(ROTSEQ_ROT(l0, 1, 0) ROTSEQ_ROT(l1, 2, 1) ROTSEQ_ROT(l2, 3, 2) ROTSEQ_ROT(l3, 4, 3)
             : "+v"(c[0]), "+v"(c[1]), "+v"(c[2]), "+v"(c[3]), "+v"(c[4])
             : ROTSEQ_COEF(OFF));
+    else
+        asm(ROTSEQ_ROT(l0, 1, 0) ROTSEQ_ROT(l1, 2, 1)
+            : "+v"(c[0]), "+v"(c[1]), "+v"(c[2])
+            : [a] "v"(a), [b] "v"(b), [l0] "n"(OFF), [l1] "n"(OFF + 1));
 }
 #undef ROTSEQ_COEF
 #undef ROTSEQ_ROT
@@ -363,7 +367,7 @@ __device__ __forceinline__ void bandwave(const ChainArgs &a, int tile, int b, in
     // (FP32 with K = 4 takes two steps per load: with four, the compiler
     // re-packs the loaded pairs with VALU moves right before their DPP reads.)
     constexpr int SPL = sizeof(T) == 4 && K == 4 ? 2 : 16 / K;
-    constexpr int NL = 4;
+    constexpr int NL = K == 2 ? 2 : 4;
     constexpr int kAhead = NL * SPL;
     static_assert(U % kAhead == 0, "coefficient ring must tile the unroll");
     static_assert(kAhead < kChainCoefPad, "look-ahead must stay inside the identity padding");
@@ -757,6 +761,7 @@ template <typename T, int ARITH>
 hipError_t chain_arith(const Plan &p, T *A, const char *ws, hipStream_t st)
 {
     switch (p.band) {
+    case 2: return go_chain<T, 2, ARITH>(p, A, ws, st);
     case 4: return go_chain<T, 4, ARITH>(p, A, ws, st);
     case 6: return go_chain<T, 6, ARITH>(p, A, ws, st);
     case 8: return go_chain<T, 8, ARITH>(p, A, ws, st);
@@ -782,6 +787,17 @@ const void *chain_kernel_fn(int band, int arith, bool batch, bool deep)
     (batch  ? (const void *)&sweep_chain_batch<T, KK, AA>                                          \
      : deep ? (const void *)&sweep_chain<T, KK, AA, true>                                          \
             : (const void *)&sweep_chain<T, KK, AA, false>)
+    if (band == 2) {  // single calls only (no batch kernel for bands of 2)
+        if (batch)
+            return nullptr;
+        const bool e = arith == kExact, f = arith == kFma;
+        return deep ? (e   ? (const void *)&sweep_chain<T, 2, kExact, true>
+                       : f ? (const void *)&sweep_chain<T, 2, kFma, true>
+                           : (const void *)&sweep_chain<T, 2, kLift, true>)
+                    : (e   ? (const void *)&sweep_chain<T, 2, kExact, false>
+                       : f ? (const void *)&sweep_chain<T, 2, kFma, false>
+                           : (const void *)&sweep_chain<T, 2, kLift, false>);
+    }
     if (band == 4)
         return arith == kExact ? ROTSEQ_CHAIN_FN(4, kExact)
                : arith == kFma ? ROTSEQ_CHAIN_FN(4, kFma)
@@ -818,6 +834,8 @@ hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds
 {
     const void *fn = esize == 8 ? chain_kernel_fn<double>(band, arith, batch, deep)
                                 : chain_kernel_fn<float>(band, arith, batch, deep);
+    if (fn == nullptr)
+        return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, waves * kWave, lds);
 }
 

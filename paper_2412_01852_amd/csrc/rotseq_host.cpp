@@ -48,6 +48,11 @@ size_t mfma_flag_bytes(int64_t m, int64_t k)
 
 }  // namespace
 
+// SIMDs of an MI355X (256 CUs x 4): the band rule of the chain kernel is
+// shape-only, so that a plan (and its workspace size) does not depend on
+// the device it is queried on.
+constexpr int64_t kChainSimds = 1024;
+
 bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok)
 {
     // The chain kernel addresses the n column signs with 32-bit byte
@@ -85,14 +90,20 @@ bool make_plan(Plan &p, int req_kernel, int req_band, bool mfma_ok)
     if (p.kernel == kChain) {
         // K = 8 by default.  With k <= 8 a single band of 8 would leave one
         // wave per row tile, which reads, rotates and writes every column;
-        // two chained bands of 4 (the second one identity rotations when
-        // k <= 4) split the A reads and writes over two waves, which is
+        // two or more chained bands (the last ones identity rotations when
+        // k is small) split the A reads and writes over two waves, which is
         // what the memory-bound regime of small k needs (32768 x 4096,
         // k = 8: 0.68 -> 0.49 ms; k = 1: 0.56 -> 0.40 ms with the
-        // streaming form).
-        if (band == 0)
-            band = p.k <= 8 ? 4 : 8;
-        if (band != 4 && band != 6 && band != 8)
+        // streaming form).  Bands of 2 halve each wave's step, which pays
+        // while their waves fit one per SIMD (1024 on MI355X; 8192^2,
+        // k = 8: 0.52 -> 0.39 ms) and in FP32 (32768 x 4096, k = 8:
+        // 0.38 -> 0.30 ms); FP64 at 2048 waves is slower (0.41 -> 0.49 ms).
+        if (band == 0) {
+            const int64_t tiles = (p.m + 63) / 64;
+            const int64_t waves2 = tiles * std::max<int64_t>(2, (p.k + 1) / 2);
+            band = p.k > 8 ? 8 : (p.esize == 4 || waves2 <= kChainSimds) ? 2 : 4;
+        }
+        if (band != 2 && band != 4 && band != 6 && band != 8)
             return false;
     } else if (p.kernel == kMultipass) {
         if (band == 0) {
@@ -292,15 +303,16 @@ double model_chain(const Plan &p, int cus)
     const double flops = 6.0 * (double)p.m * (double)(p.n - 1) * (double)p.k;
     const double bytes = 2.0 * (double)p.m * (double)p.n * (double)p.esize;
     if (p.npass <= kChainDeepBands) {
-        // Streaming form: a lone wave's step costs about 78 ns with bands of
-        // 4 and 120 ns with bands of 8 (one wave issues at most one
-        // instruction per 4 cycles); each further wave per SIMD adds 3/4 of
-        // that, unless HBM (about 5 TB/s for this mix of reads and writes)
-        // takes longer.  Fitted to FP64 sweeps of m = 1024 .. 65536,
+        // Streaming form: a lone wave's step costs about 55 ns with bands of
+        // 2, 78 ns with bands of 4 and 120 ns with bands of 8 (one wave
+        // issues at most one instruction per 4 cycles); each further wave
+        // per SIMD adds 3/4 of that, unless HBM (about 5 TB/s for this mix
+        // of reads and writes) takes longer.  Fitted to FP64 sweeps of m = 1024 .. 65536,
         // n = 1024 .. 16384, k = 1 .. 32.
         const double waves = (double)((p.m + 63) / 64) * (double)p.npass;
         const double per_simd = std::max(1.0, std::ceil(waves / (4.0 * (double)cus)));
-        const double step = (p.band <= 4 ? 78e-9 : 120e-9) * (1.0 + 0.75 * (per_simd - 1.0));
+        const double step = (p.band <= 2 ? 55e-9 : p.band <= 4 ? 78e-9 : 120e-9) *
+                            (1.0 + 0.75 * (per_simd - 1.0));
         return std::max((double)p.steps * step, bytes / 5.0e12) + 15e-6;
     }
     const double lat = (double)(p.n + p.k) * 0.11e-6;

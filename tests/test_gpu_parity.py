@@ -102,7 +102,7 @@ CHAIN = [
     # band, waves, publish: waves=1 puts every hand-off through A and the
     # device-scope counters; publish=1 publishes after every column.
     (4, 0, 0), (6, 0, 0), (8, 0, 0), (8, 1, 1), (4, 1, 32), (6, 2, 4), (8, 3, 2),
-    (4, 5, 8), (6, 16, 0), (8, 16, 1), (4, 7, 64),
+    (4, 5, 8), (6, 16, 0), (8, 16, 1), (4, 7, 64), (2, 0, 0), (2, 3, 4), (2, 16, 1),
 ]
 
 

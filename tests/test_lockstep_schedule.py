@@ -81,7 +81,7 @@ def deep_constants():
     return get("G_deep"), get("RB_deep"), get("H_deep"), (int(m.group(1)), int(m.group(2)))
 
 
-@pytest.mark.parametrize("K", [4, 6, 8])
+@pytest.mark.parametrize("K", [2, 4, 6, 8])
 @pytest.mark.parametrize("steps", [32, 64, 4128])
 def test_streaming_lag_is_safe_and_smallest(K, steps):
     g, rb, h, (lg8, lg) = deep_constants()
@@ -92,18 +92,18 @@ def test_streaming_lag_is_safe_and_smallest(K, steps):
         assert violations(K, lag - 1, steps, g, rb), "a smaller lag would do"
 
 
-@pytest.mark.parametrize("K", [4, 6, 8])
+@pytest.mark.parametrize("K", [2, 4, 6, 8])
 @pytest.mark.parametrize("steps", [16, 32, 10256])
 def test_kernel_lag_is_safe(K, steps):
     assert violations(K, kernel_lag(K), steps) == []
 
 
-@pytest.mark.parametrize("K", [4, 6, 8])
+@pytest.mark.parametrize("K", [2, 4, 6, 8])
 def test_kernel_lag_is_smallest(K):
     assert violations(K, kernel_lag(K) - 1, 10256), "a smaller lag would do"
 
 
-@pytest.mark.parametrize("K", [4, 6, 8])
+@pytest.mark.parametrize("K", [2, 4, 6, 8])
 def test_too_much_lag_overwrites(K):
     """The ring bounds the lag from above too: the model sees overwrites."""
     assert any(kind == "overwritten before read"
@@ -165,7 +165,7 @@ def workgroup_barriers(g, W, tiles, nbands, steps, lg, dg):
     return counts
 
 
-@pytest.mark.parametrize("K", [4, 6, 8])
+@pytest.mark.parametrize("K", [2, 4, 6, 8])
 @pytest.mark.parametrize("W,tiles,nbands", [(1, 3, 5), (2, 5, 3), (8, 7, 24), (16, 160, 24),
                                            (16, 3, 5), (15, 11, 40), (16, 2, 100)])
 def test_every_wave_passes_the_same_barriers(K, W, tiles, nbands):
