@@ -318,8 +318,11 @@ def bench_served(args):
     import queue
     import threading
     import numpy as np
+    import torch
     import paper_2412_01852_amd as rs
     from paper_2412_01852_amd.inputs import served_requests
+
+    torch.zeros(1, device="cuda:0")  # torch's device context first (the plain-call loop uses it)
 
     wl = SERVED[args.workload]
     rng = np.random.Generator(np.random.PCG64(wl["seed"] + 77))
@@ -375,12 +378,47 @@ def bench_served(args):
             raise RuntimeError(f"served run failed: {errors[:3]}")
         return wall, lat_req
 
+    def sweeps_of(r):
+        """(k, C, S) of each sweep of request r, as the clients draw them."""
+        n, k = r["n"], r["k"]
+        state = r["seed"].generate_state(r["sweeps"] + 1)
+        off = int(state[0]) % (len(theta) - span - 1)
+        for sw in range(r["sweeps"]):
+            if args.k_per_sweep:
+                k = int(wl["ks"][int(state[sw + 1]) % len(wl["ks"])])
+            o = (off + sw * 7919 * k) % (len(theta) - span - 1)
+            yield (k, c_pool[o:o + (n - 1) * k].reshape((n - 1, k), order="F"),
+                   s_pool[o:o + (n - 1) * k].reshape((n - 1, k), order="F"))
+
+    def plain_loop(reqs_):
+        """The same requests as plain calls, one after another on one stream
+        (matrix upload, then per sweep C/S upload and rotseq): wall seconds
+        and flops."""
+        import torch
+        flops_ = 0.0
+        t0 = time.perf_counter()
+        for r in reqs_:
+            n = r["n"]
+            A = rs.device_colmajor(a_pool[:n, :n].copy(order="F"), "cuda:0")
+            for k, C, S in sweeps_of(r):
+                rs.rotseq(A, rs.device_colmajor(C.copy(order="F"), "cuda:0"),
+                          rs.device_colmajor(S.copy(order="F"), "cuda:0"))
+                flops_ += 6.0 * n * (n - 1) * k
+            del A
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, flops_
+
     kw = dict(n_lo=wl["n_lo"], n_hi=wl["n_hi"], sweeps=wl["sweeps"], ks=wl["ks"])
     cal = served_requests(128, seed=wl["seed"] + 1000, **kw)
     with rs.Server(budget_bytes=wl["budget"]) as srv:
         run(srv, cal[:16], [0.0] * 16)  # warm-up
+        f0 = srv.stats()["flops"]
         wall_cal, _ = run(srv, cal, [0.0] * len(cal))
+        flops_cal = srv.stats()["flops"] - f0
     sat_rate = len(cal) / wall_cal  # requests per second when saturated
+    # The calibration requests again as repeated plain calls (closed loop).
+    plain_loop(cal[:4])  # warm-up
+    wall_plain, flops_plain = plain_loop(cal)
     rate = wl["load"] * sat_rate
     reqs = served_requests(args.requests, seed=wl["seed"], rate_per_s=rate, **kw)
     arrivals = [r["arrival"] for r in reqs]
@@ -422,6 +460,15 @@ def bench_served(args):
             "peak_resident_bytes": st["peak_resident_bytes"],
             "saturated_requests_per_s": round(sat_rate, 3),
             "server_busy_gflops": round(st["gflops"], 2),
+            "saturated_gflops": round(flops_cal / wall_cal / 1e9, 2),
+        },
+        # The 128 calibration requests, served saturated vs as repeated plain
+        # calls on one stream (both include the host-to-device copies of C/S).
+        "plain_calls": {
+            "requests": len(cal),
+            "wall_s": round(wall_plain, 3),
+            "gflops": round(flops_plain / wall_plain / 1e9, 2),
+            "served_saturated_wall_s": round(wall_cal, 3),
         },
     }
     print(json.dumps(out), flush=True)
