@@ -36,9 +36,13 @@ def _load(path=None):
         f = getattr(lib, name)
         f.restype = None
         f.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
-    f = lib.oracle_refl3seq_d
+    for name in ("oracle_refl3seq_d", "oracle_refl3seq_inverse_d"):
+        f = getattr(lib, name)
+        f.restype = None
+        f.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64]
+    f = lib.oracle_refl3seq_left_d
     f.restype = None
-    f.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64]
+    f.argtypes = [i64, i64, i64, ctypes.c_int, dp, i64, dp, i64, dp, i64, dp, i64]
     f = lib.oracle_rotseq_threads_d
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.c_int, i64, i64, i64, dp, i64, dp, i64, dp, i64]
@@ -133,21 +137,31 @@ def reflseq(A, TAU, NU, *, lib=None, inverse=False, left=False):
     return A
 
 
-def refl3seq(A, TAU, NU1, NU2, *, lib=None):
+def refl3seq(A, TAU, NU1, NU2, *, inverse=False, left=False, lib=None):
     """Apply a sequence of 3x3 reflectors in place: reflector (j, p) is
     I - tau v v^T with v = e_j + nu1 e_{j+1} + nu2 e_{j+2} acting on
-    columns j..j+2; TAU, NU1, NU2 are (n-2) x k.  Returns ``A``."""
+    columns j..j+2 (rows with ``left``); TAU, NU1, NU2 are (n-2) x k
+    ((m-2) x k with ``left``).  Forward: A H(0,0) ... H(n-3,k-1);
+    ``inverse``: A H(n-3,k-1) ... H(0,0); ``left``: H(m-3,k-1) ... H(0,0) A,
+    and with ``inverse`` H(0,0) ... H(m-3,k-1) A.  Returns ``A``."""
     lib = lib or _load()
     m, n = A.shape
     nm2, k = TAU.shape
+    r = m if left else n
     if NU1.shape != TAU.shape or NU2.shape != TAU.shape:
         raise ValueError("TAU, NU1 and NU2 must have the same shape")
-    if n >= 2 and nm2 != max(n - 2, 0):
-        raise ValueError(f"TAU has {nm2} rows, expected n-2 = {n - 2}")
-    if m == 0 or n <= 2 or k == 0:
+    if r >= 2 and nm2 != max(r - 2, 0):
+        raise ValueError(f"TAU has {nm2} rows, expected {r - 2}")
+    if (n == 0 if left else m == 0) or r <= 2 or k == 0:
         return A
-    lib.oracle_refl3seq_d(m, n, k, _ptr(A), _ld(A, "A"), _ptr(TAU), _ld(TAU, "TAU"),
-                          _ptr(NU1), _ld(NU1, "NU1"), _ptr(NU2), _ld(NU2, "NU2"))
+    args = (_ptr(A), _ld(A, "A"), _ptr(TAU), _ld(TAU, "TAU"),
+            _ptr(NU1), _ld(NU1, "NU1"), _ptr(NU2), _ld(NU2, "NU2"))
+    if left:
+        lib.oracle_refl3seq_left_d(m, n, k, 1 if inverse else 0, *args)
+    elif inverse:
+        lib.oracle_refl3seq_inverse_d(m, n, k, *args)
+    else:
+        lib.oracle_refl3seq_d(m, n, k, *args)
     return A
 
 

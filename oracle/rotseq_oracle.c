@@ -279,3 +279,62 @@ void oracle_refl3seq_d(int64_t m, int64_t n, int64_t k,
             }
         }
 }
+
+/*
+ * The inverse order: A <- A * (H(0,0) ... H(n-3,k-1))^T
+ *                     = A * H(n-3,k-1) ... H(1,0) H(0,0)
+ * (each H is symmetric), i.e. p descending and, within p, j descending,
+ * with the per-row formula above.  For orthogonal reflectors it undoes a
+ * forward call.
+ */
+void oracle_refl3seq_inverse_d(int64_t m, int64_t n, int64_t k,
+                               double *A, int64_t lda,
+                               const double *TAU, int64_t ldt,
+                               const double *NU1, int64_t ld1,
+                               const double *NU2, int64_t ld2)
+{
+    for (int64_t p = k - 1; p >= 0; --p)
+        for (int64_t j = n - 3; j >= 0; --j) {
+            double tau = TAU[j + p * ldt], nu1 = NU1[j + p * ld1], nu2 = NU2[j + p * ld2];
+            double t1 = tau * nu1, t2 = tau * nu2;
+            double *x = &A[j * lda], *y = &A[(j + 1) * lda], *z = &A[(j + 2) * lda];
+            for (int64_t i = 0; i < m; ++i) {
+                double w = x[i] + nu1 * y[i] + nu2 * z[i];
+                x[i] = x[i] - tau * w;
+                y[i] = y[i] - t1 * w;
+                z[i] = z[i] - t2 * w;
+            }
+        }
+}
+
+/*
+ * Application from the left (reflector (j, p) mixes ROWS j, j+1, j+2;
+ * TAU, NU1, NU2 are (m-2) x k):
+ *   forward: A <- (H(0,0) ... H(m-3,k-1))^T A = H(m-3,k-1) ... H(0,0) A,
+ *            so H(0,0) meets A first: p ascending, j ascending;
+ *   inverse: A <- H(0,0) ... H(m-3,k-1) A: p descending, j descending.
+ * Per column i, with (x, y, z) = (A(j,i), A(j+1,i), A(j+2,i)), the same
+ * formula as above.
+ */
+void oracle_refl3seq_left_d(int64_t m, int64_t n, int64_t k, int inverse,
+                            double *A, int64_t lda,
+                            const double *TAU, int64_t ldt,
+                            const double *NU1, int64_t ld1,
+                            const double *NU2, int64_t ld2)
+{
+    for (int64_t pp = 0; pp < k; ++pp)
+        for (int64_t jj = 0; jj + 2 < m; ++jj) {
+            const int64_t p = inverse ? k - 1 - pp : pp;
+            const int64_t j = inverse ? m - 3 - jj : jj;
+            double tau = TAU[j + p * ldt], nu1 = NU1[j + p * ld1], nu2 = NU2[j + p * ld2];
+            double t1 = tau * nu1, t2 = tau * nu2;
+            for (int64_t i = 0; i < n; ++i) {
+                double *col = &A[i * lda];
+                double w = col[j] + nu1 * col[j + 1] + nu2 * col[j + 2];
+                col[j] = col[j] - tau * w;
+                col[j + 1] = col[j + 1] - t1 * w;
+                col[j + 2] = col[j + 2] - t2 * w;
+            }
+        }
+}
+
