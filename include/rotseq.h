@@ -283,7 +283,8 @@ int rotseq_refl_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
  * rotseq_refl3_workspace_bytes() bytes, 256-byte aligned (NULL: the library
  * keeps one per device and stream; ROTSEQ_E_WORKSPACE if too small or
  * misaligned).  ROTSEQ_E_UNSUPPORTED if m > 2^31 - 65 or n > 2^30 - 1.
- * Only the right application in the forward order is provided.
+ * Right application in the forward order; rotseq_refl3_ex_* below also
+ * takes the inverse order and application from the left.
  */
 int rotseq_refl3_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
                    const double *TAU, int64_t ldt, const double *NU1, int64_t ld1,
@@ -296,6 +297,37 @@ int rotseq_refl3_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
 /* Workspace bytes of rotseq_refl3_{d,s} for this shape (dtype 'd' or 's');
  * 0 for quick-return shapes.  Host-only. */
 size_t rotseq_refl3_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k);
+
+/*
+ * rotseq_refl3_ex_d / rotseq_refl3_ex_s: rotseq_refl3_{d,s} with options
+ * (Section 4.3 of the paper for the side; the inverse order as for
+ * rotations).  Arguments 1-12 and the workspace (14-15) as for
+ * rotseq_refl3_d; 13 opts (host, may be NULL = forward, right), of which
+ * only `inverse` and `left` may be set (every other field 0, else
+ * ROTSEQ_E_UNSUPPORTED):
+ *   inverse  A <- A * (H(0,0) ... H(n-3,k-1))^T = A * H(n-3,k-1) ... H(0,0),
+ *            the same reflectors with p and j descending (each H is
+ *            symmetric); for orthogonal reflectors it undoes a forward call.
+ *   left     reflector (j,p) mixes ROWS j, j+1, j+2 (TAU, NU1, NU2 are then
+ *            (m-2) x k, leading dimensions >= max(1, m-2)), with the same
+ *            per-column formula:  A <- (H(0,0) ... H(m-3,k-1))^T A
+ *            = H(m-3,k-1) ... H(0,0) A, and with `inverse`
+ *            A <- H(0,0) ... H(m-3,k-1) A.  The library packs A transposed
+ *            into the workspace (m*n more elements), sweeps the packed copy
+ *            and unpacks it.  Quick return if n == 0, m <= 2 or k == 0.
+ */
+int rotseq_refl3_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
+                      const double *TAU, int64_t ldt, const double *NU1, int64_t ld1,
+                      const double *NU2, int64_t ld2, hipStream_t stream,
+                      const rotseq_opts *opts, void *workspace, size_t ws_bytes);
+int rotseq_refl3_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
+                      const float *TAU, int64_t ldt, const float *NU1, int64_t ld1,
+                      const float *NU2, int64_t ld2, hipStream_t stream,
+                      const rotseq_opts *opts, void *workspace, size_t ws_bytes);
+/* Workspace bytes of rotseq_refl3_ex_{d,s} for this shape and options (A with
+ * lda = m); 0 for quick-return shapes and unsupported options.  Host-only. */
+size_t rotseq_refl3_ex_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k,
+                                       const rotseq_opts *opts);
 
 /*
  * Device workspace bytes needed by rotseq_ex_{d,s} and rotseq_refl_ex_{d,s}

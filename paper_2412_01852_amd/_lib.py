@@ -163,8 +163,14 @@ def _load():
         f = getattr(lib, name)
         f.restype, f.argtypes = i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp,
                                       ctypes.c_size_t]
+    for name in ("rotseq_refl3_ex_d", "rotseq_refl3_ex_s"):
+        f = getattr(lib, name)
+        f.restype, f.argtypes = i32, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp,
+                                      ctypes.POINTER(Options), vp, ctypes.c_size_t]
     lib.rotseq_refl3_workspace_bytes.restype = ctypes.c_size_t
     lib.rotseq_refl3_workspace_bytes.argtypes = [ctypes.c_char, i64, i64, i64]
+    lib.rotseq_refl3_ex_workspace_bytes.restype = ctypes.c_size_t
+    lib.rotseq_refl3_ex_workspace_bytes.argtypes = [ctypes.c_char, i64, i64, i64, ctypes.POINTER(Options)]
     lib.rotseq_workspace_bytes.restype = ctypes.c_size_t
     lib.rotseq_workspace_bytes.argtypes = [ctypes.c_char, i64, i64, i64, ctypes.POINTER(Options)]
     lib.rotseq_check_args.restype = i32
@@ -313,11 +319,12 @@ def reflseq(A, TAU, NU, *, opts=None, workspace=None, stream=None):
     return _call(True, A, TAU, NU, opts, workspace, stream)
 
 
-def refl3seq(A, TAU, NU1, NU2, *, workspace=None, stream=None):
+def refl3seq(A, TAU, NU1, NU2, *, opts=None, workspace=None, stream=None):
     """A <- A * H(0,0) ... H(n-3,k-1) for 3x3 reflectors H = I - tau v v^T,
     v = e_j + nu1 e_{j+1} + nu2 e_{j+2} (rotseq_refl3_*).  A: (m, n)
     float64/float32 column-major device tensor; TAU, NU1, NU2: (n-2, k) of
-    the same dtype.  Returns A."""
+    the same dtype ((m-2, k) with ``opts["left"]``).  ``opts`` may ask for
+    ``inverse`` and ``left`` (rotseq_refl3_ex_*).  Returns A."""
     import torch
     if A.dtype not in (torch.float64, torch.float32):
         raise TypeError("A must be float64 or float32")
@@ -325,8 +332,9 @@ def refl3seq(A, TAU, NU1, NU2, *, workspace=None, stream=None):
         raise TypeError("A and the coefficient arrays must share a dtype")
     m, n = A.shape
     k = TAU.shape[1]
-    if TAU.shape != NU1.shape or TAU.shape != NU2.shape or TAU.shape[0] != max(n - 2, 0):
-        raise ValueError(f"coefficient arrays must be ({max(n - 2, 0)}, k); got "
+    r = m if _is_left(opts) else n
+    if TAU.shape != NU1.shape or TAU.shape != NU2.shape or TAU.shape[0] != max(r - 2, 0):
+        raise ValueError(f"coefficient arrays must be ({max(r - 2, 0)}, k); got "
                          f"{tuple(TAU.shape)}, {tuple(NU1.shape)}, {tuple(NU2.shape)}")
     for t, nm in ((A, "A"), (TAU, "TAU"), (NU1, "NU1"), (NU2, "NU2")):
         if t.numel() and not t.is_cuda:
@@ -334,20 +342,27 @@ def refl3seq(A, TAU, NU1, NU2, *, workspace=None, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(A.device)
     ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
     lib = _load()
-    fn = lib.rotseq_refl3_d if A.dtype == torch.float64 else lib.rotseq_refl3_s
     wptr = workspace.data_ptr() if workspace is not None else None
     wbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
-    rc = fn(m, n, k, ptr(A), _ld(A, "A"), ptr(TAU), _ld(TAU, "TAU"), ptr(NU1), _ld(NU1, "NU1"),
-            ptr(NU2), _ld(NU2, "NU2"), ctypes.c_void_p(st.cuda_stream), wptr, wbytes)
+    args = (m, n, k, ptr(A), _ld(A, "A"), ptr(TAU), _ld(TAU, "TAU"), ptr(NU1), _ld(NU1, "NU1"),
+            ptr(NU2), _ld(NU2, "NU2"), ctypes.c_void_p(st.cuda_stream))
+    if opts is None:
+        fn = lib.rotseq_refl3_d if A.dtype == torch.float64 else lib.rotseq_refl3_s
+        rc = fn(*args, wptr, wbytes)
+    else:
+        fn = lib.rotseq_refl3_ex_d if A.dtype == torch.float64 else lib.rotseq_refl3_ex_s
+        rc = fn(*args, _opts(opts), wptr, wbytes)
     if rc != 0:
         raise RotseqError(rc, "refl3seq")
     return A
 
 
-def refl3_workspace_bytes(dtype, m, n, k):
+def refl3_workspace_bytes(dtype, m, n, k, opts=None):
     ch = {"float64": b"d", "double": b"d", "d": b"d", "float32": b"s", "float": b"s", "s": b"s"}[
         str(dtype).replace("torch.", "")]
-    return _load().rotseq_refl3_workspace_bytes(ch, m, n, k)
+    if opts is None:
+        return _load().rotseq_refl3_workspace_bytes(ch, m, n, k)
+    return _load().rotseq_refl3_ex_workspace_bytes(ch, m, n, k, _opts(opts))
 
 
 def _call(refl, A, C, S, opts, workspace, stream):

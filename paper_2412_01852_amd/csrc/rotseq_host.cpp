@@ -695,59 +695,108 @@ int run(int kind, int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *C
 }
 
 // Sequences of 3x3 reflectors: arguments checked in the order of
-// rotseq_refl3_d, then the records are prepared and the bands swept.
+// rotseq_refl3_ex_d, then the records are prepared and the bands swept.
+// The inverse order sweeps a column-reversed view of A (negative leading
+// dimension) with the reflectors read backwards; left application sweeps a
+// transposed copy of A packed after the records in the workspace.
+bool refl3_opts_ok(const rotseq_opts *o)
+{
+    return o == nullptr || (o->arith == ROTSEQ_ARITH_AUTO && o->kernel == ROTSEQ_KERNEL_AUTO &&
+                            o->band == 0 && o->waves == 0 && o->publish == 0 && o->shape == 0);
+}
+
+// Workspace of a 3x3 reflector call: the records, then (left application)
+// the packed transposed copy.  False for shapes the sweep does not index.
+bool refl3_layout(Refl3Plan &p, size_t &off_pack, size_t &total, int64_t m, int64_t n, int64_t k,
+                  int64_t lda, int esize, bool left)
+{
+    if (!refl3_plan(p, left ? n : m, left ? m : n, k, left ? n : lda, esize))
+        return false;
+    off_pack = (p.total + 255) & ~(size_t)255;
+    total = left ? off_pack + (((size_t)m * (size_t)n * (size_t)esize + 255) & ~(size_t)255) : p.total;
+    return true;
+}
+
 template <typename T>
 int run_refl3(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, int64_t ldt,
-              const T *NU1, int64_t ld1, const T *NU2, int64_t ld2, hipStream_t stream, void *ws,
-              size_t ws_bytes)
+              const T *NU1, int64_t ld1, const T *NU2, int64_t ld2, hipStream_t stream,
+              const rotseq_opts *opts, void *ws, size_t ws_bytes)
 {
+    const bool left = opts && opts->left, inverse = opts && opts->inverse;
+    const int64_t r = left ? m : n;  // the dimension the reflectors mix
     if (m < 0)
         return -1;
     if (n < 0)
         return -2;
     if (k < 0)
         return -3;
-    const bool work = m > 0 && n > 2 && k > 0;
-    const int64_t n2 = n > 2 ? n - 2 : 1;
+    const bool work = (left ? n > 0 : m > 0) && r > 2 && k > 0;
+    const int64_t r2 = r > 2 ? r - 2 : 1;
     if (work && A == nullptr)
         return -4;
     if (lda < (m > 1 ? m : 1))
         return -5;
     if (work && TAU == nullptr)
         return -6;
-    if (ldt < n2)
+    if (ldt < r2)
         return -7;
     if (work && NU1 == nullptr)
         return -8;
-    if (ld1 < n2)
+    if (ld1 < r2)
         return -9;
     if (work && NU2 == nullptr)
         return -10;
-    if (ld2 < n2)
+    if (ld2 < r2)
         return -11;
+    if (!refl3_opts_ok(opts))
+        return ROTSEQ_E_UNSUPPORTED;
     if (!work)
         return ROTSEQ_SUCCESS;
     Refl3Plan p;
-    if (!refl3_plan(p, m, n, k, lda, (int)sizeof(T)))
+    size_t off_pack = 0, total = 0;
+    if (!refl3_layout(p, off_pack, total, m, n, k, lda, (int)sizeof(T), left))
         return ROTSEQ_E_UNSUPPORTED;
     if (ws) {
-        if (ws_bytes < p.total || ((uintptr_t)ws & 255) != 0)
+        if (ws_bytes < total || ((uintptr_t)ws & 255) != 0)
             return ROTSEQ_E_WORKSPACE;
     } else {
-        const int rc = pool().get(stream, p.total, &ws);
+        const int rc = pool().get(stream, total, &ws);
         if (rc)
             return rc;
     }
+    // The swept matrix: A itself, or its transpose packed in the workspace
+    // (p.m x p.n, leading dimension p.lda).
+    T *X = left ? (T *)((char *)ws + off_pack) : A;
+    if (left && launch_transpose(A, m, n, lda, X, p.lda, (int)sizeof(T), stream) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    int64_t cj = 1;
+    if (inverse) {
+        // Reversed columns and reflectors: view column c is column p.n-1-c,
+        // record (j, q) is reflector (p.n-3-j, k-1-q).
+        X += (p.n - 1) * p.lda;
+        p.lda = -p.lda;
+        TAU += (r - 3) + (k - 1) * ldt;
+        NU1 += (r - 3) + (k - 1) * ld1;
+        NU2 += (r - 3) + (k - 1) * ld2;
+        ldt = -ldt;
+        ld1 = -ld1;
+        ld2 = -ld2;
+        cj = -1;
+    }
     Profiler::Rec rec{};
     const bool timed = profiler().begin(rec, stream);
-    if (launch_refl3_prep(p, TAU, ldt, NU1, ld1, NU2, ld2, ws, stream) != hipSuccess)
+    if (launch_refl3_prep(p, TAU, ldt, NU1, ld1, NU2, ld2, cj, ws, stream) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (timed)
         (void)hipEventRecord(rec.e1, stream);
-    if (launch_refl3_sweep(p, A, ws, stream) != hipSuccess)
+    if (launch_refl3_sweep(p, X, ws, inverse, stream) != hipSuccess)
+        return ROTSEQ_E_HIP;
+    if (timed)
+        (void)hipEventRecord(rec.e2, stream);
+    if (left && launch_transpose((T *)((char *)ws + off_pack), n, m, n, A, lda, (int)sizeof(T),
+                                 stream) != hipSuccess)
         return ROTSEQ_E_HIP;
     if (timed) {
-        (void)hipEventRecord(rec.e2, stream);
         (void)hipEventRecord(rec.e3, stream);
         profiler().finish(rec);
     }
@@ -838,25 +887,52 @@ int rotseq_refl3_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, cons
                    int64_t ldt, const double *NU1, int64_t ld1, const double *NU2, int64_t ld2,
                    hipStream_t stream, void *workspace, size_t ws_bytes)
 {
-    return run_refl3<double>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, workspace,
-                             ws_bytes);
+    return run_refl3<double>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, nullptr,
+                             workspace, ws_bytes);
 }
 
 int rotseq_refl3_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, const float *TAU,
                    int64_t ldt, const float *NU1, int64_t ld1, const float *NU2, int64_t ld2,
                    hipStream_t stream, void *workspace, size_t ws_bytes)
 {
-    return run_refl3<float>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, workspace,
-                            ws_bytes);
+    return run_refl3<float>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, nullptr,
+                            workspace, ws_bytes);
+}
+
+int rotseq_refl3_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const double *TAU,
+                      int64_t ldt, const double *NU1, int64_t ld1, const double *NU2, int64_t ld2,
+                      hipStream_t stream, const rotseq_opts *opts, void *workspace, size_t ws_bytes)
+{
+    return run_refl3<double>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, opts,
+                             workspace, ws_bytes);
+}
+
+int rotseq_refl3_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, const float *TAU,
+                      int64_t ldt, const float *NU1, int64_t ld1, const float *NU2, int64_t ld2,
+                      hipStream_t stream, const rotseq_opts *opts, void *workspace, size_t ws_bytes)
+{
+    return run_refl3<float>(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, stream, opts,
+                            workspace, ws_bytes);
 }
 
 size_t rotseq_refl3_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k)
 {
+    return rotseq_refl3_ex_workspace_bytes(dtype, m, n, k, nullptr);
+}
+
+size_t rotseq_refl3_ex_workspace_bytes(char dtype, int64_t m, int64_t n, int64_t k,
+                                       const rotseq_opts *opts)
+{
     const int esize = dtype == 'd' ? 8 : dtype == 's' ? 4 : 0;
-    Refl3Plan p;
-    if (!esize || !refl3_plan(p, m, n, k, m > 1 ? m : 1, esize))
+    const bool left = opts && opts->left;
+    const int64_t r = left ? m : n;
+    if (!esize || k <= 0 || r <= 2 || (left ? n <= 0 : m <= 0) || !refl3_opts_ok(opts))
         return 0;
-    return p.total;
+    Refl3Plan p;
+    size_t off_pack = 0, total = 0;
+    if (!refl3_layout(p, off_pack, total, m, n, k, m > 1 ? m : 1, esize, left))
+        return 0;
+    return total;
 }
 
 int rotseq_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, const double *C, int64_t ldc,

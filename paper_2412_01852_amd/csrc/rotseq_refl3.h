@@ -20,8 +20,14 @@ struct Refl3Plan {
 // Fills `p` for a call with work (m > 0, n > 2, k > 0); false if the shape
 // is outside what the kernel indexes with 32-bit integers.  Host-only.
 bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int esize);
+// cj: step between the records of reflectors j and j+1 in TAU, NU1, NU2
+// (1, or -1 with negative leading dimensions: the inverse order).
 hipError_t launch_refl3_prep(const Refl3Plan &p, const void *TAU, int64_t ldt, const void *NU1,
-                             int64_t ld1, const void *NU2, int64_t ld2, void *ws, hipStream_t stream);
-hipError_t launch_refl3_sweep(const Refl3Plan &p, void *A, const void *ws, hipStream_t stream);
+                             int64_t ld1, const void *NU2, int64_t ld2, int64_t cj, void *ws,
+                             hipStream_t stream);
+// rev: A is a column-reversed view (negative lda) and the reflectors are
+// read in the inverse order, so each one's unit component is its third column.
+hipError_t launch_refl3_sweep(const Refl3Plan &p, void *A, const void *ws, bool rev,
+                              hipStream_t stream);
 
 }  // namespace rotseq

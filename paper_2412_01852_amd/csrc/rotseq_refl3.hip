@@ -141,10 +141,12 @@ __device__ __forceinline__ void reflect3_dpp32(float &x, float &y, float &z, flo
 // t and member q, rec[((g * steps + t) * K + q) * 5 + {0..4}] holds
 // (nu1, nu2, -tau, -tau nu1, -tau nu2) of reflector (t - 2q, gK + q), or
 // zeros where that reflector does not exist (the sweep never applies those).
+// Reflector (j, p) is read at TAU[j*cj + p*ldt] (likewise NU1, NU2): cj = -1
+// with negative leading dimensions reads the reflectors in the inverse order.
 template <typename T>
 __global__ void refl3_prep(const T *__restrict__ TAU, int64_t ldt, const T *__restrict__ NU1,
-                           int64_t ld1, const T *__restrict__ NU2, int64_t ld2, int64_t n, int64_t k,
-                           int K, int steps, int64_t total, T *__restrict__ rec)
+                           int64_t ld1, const T *__restrict__ NU2, int64_t ld2, int64_t cj, int64_t n,
+                           int64_t k, int K, int steps, int64_t total, T *__restrict__ rec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total)
@@ -155,9 +157,9 @@ __global__ void refl3_prep(const T *__restrict__ TAU, int64_t ldt, const T *__re
     const int64_t j = t - 2 * q, p = g * K + q;
     T tau = T(0), nu1 = T(0), nu2 = T(0);
     if (j >= 0 && j < n - 2 && p < k) {
-        tau = TAU[j + p * ldt];
-        nu1 = NU1[j + p * ld1];
-        nu2 = NU2[j + p * ld2];
+        tau = TAU[j * cj + p * ldt];
+        nu1 = NU1[j * cj + p * ld1];
+        nu2 = NU2[j * cj + p * ld2];
     }
     T *out = rec + kRec * i;
     out[0] = nu1;
@@ -168,7 +170,7 @@ __global__ void refl3_prep(const T *__restrict__ TAU, int64_t ldt, const T *__re
 }
 
 struct Refl3Args {
-    uint64_t A;            // T*, column-major, lda
+    uint64_t A;            // T*, column-major, lda (negative: a column-reversed view)
     int64_t lda;
     uint64_t rec;          // records of this launch's first band
     int64_t band_stride;   // elements between the records of neighbouring bands
@@ -183,7 +185,10 @@ constexpr int kRefl3MaxWaves = 12;
 // the registers with bands of 4.
 constexpr int refl3_band(int esize) { return esize == 8 ? 8 : 4; }
 
-template <typename T, int K>
+// REV: the reflectors of a column-reversed view (the inverse order): the
+// reflector at view columns c, c+1, c+2 has its unit component on c+2, so
+// the formula runs with the roles of the first and third column swapped.
+template <typename T, int K, bool REV>
 __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
 {
     using Gm = R3Geom<K>;
@@ -323,12 +328,11 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
                         a2 = rd[set][(e + 2) / BLK][(e + 2) % PER],
                         a3 = rd[set][(e + 3) / BLK][(e + 3) % PER],
                         a4 = rd[set][(e + 4) / BLK][(e + 4) % PER];
+                T &c0 = x[REV ? (s + 2) % R : s], &c2 = x[REV ? s : (s + 2) % R];
                 if constexpr (sizeof(T) == 8)
-                    reflect3_dpp<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1, a2, a3,
-                                                     a4);
+                    reflect3_dpp<L0, L1, L2, L3, L4>(c0, x[(s + 1) % R], c2, a0, a1, a2, a3, a4);
                 else
-                    reflect3_dpp32<L0, L1, L2, L3, L4>(x[s], x[(s + 1) % R], x[(s + 2) % R], a0, a1, a2,
-                                                       a3, a4);
+                    reflect3_dpp32<L0, L1, L2, L3, L4>(c0, x[(s + 1) % R], c2, a0, a1, a2, a3, a4);
             });
             const int c = t - 2 * K + 2;
             const T v = x[(u - 2 * K + 2 + 2 * R) % R];
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(kRefl3MaxWaves * 64) void refl3_sweep(Refl3Args a)
         r3_barrier();
 }
 
-template <typename T, int K>
+template <typename T, int K, bool REV>
 hipError_t sweep_launches(const Refl3Plan &p, T *A, const T *rec, hipStream_t st)
 {
     using Gm = R3Geom<K>;
@@ -378,7 +382,7 @@ hipError_t sweep_launches(const Refl3Plan &p, T *A, const T *rec, hipStream_t st
         a.n = (int)p.n;
         a.chunks = p.steps / Gm::R;
         const size_t lds = W > 1 ? (size_t)(W - 1) * Gm::RB * kWave * sizeof(T) : 4;
-        refl3_sweep<T, K><<<tiles, W * kWave, lds, st>>>(a);
+        refl3_sweep<T, K, REV><<<tiles, W * kWave, lds, st>>>(a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -412,28 +416,31 @@ bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int 
 }
 
 hipError_t launch_refl3_prep(const Refl3Plan &p, const void *TAU, int64_t ldt, const void *NU1,
-                             int64_t ld1, const void *NU2, int64_t ld2, void *ws, hipStream_t st)
+                             int64_t ld1, const void *NU2, int64_t ld2, int64_t cj, void *ws,
+                             hipStream_t st)
 {
     const int B = 256;
     const int64_t total = p.rec_elems / kRec;
     const unsigned blocks = (unsigned)((total + B - 1) / B);
     if (p.esize == 8)
         refl3_prep<double><<<blocks, B, 0, st>>>((const double *)TAU, ldt, (const double *)NU1, ld1,
-                                                 (const double *)NU2, ld2, p.n, p.k, p.band, p.steps,
-                                                 total, (double *)ws);
+                                                 (const double *)NU2, ld2, cj, p.n, p.k, p.band,
+                                                 p.steps, total, (double *)ws);
     else
         refl3_prep<float><<<blocks, B, 0, st>>>((const float *)TAU, ldt, (const float *)NU1, ld1,
-                                               (const float *)NU2, ld2, p.n, p.k, p.band, p.steps,
-                                               total, (float *)ws);
+                                               (const float *)NU2, ld2, cj, p.n, p.k, p.band,
+                                               p.steps, total, (float *)ws);
     return hipGetLastError();
 }
 
-hipError_t launch_refl3_sweep(const Refl3Plan &p, void *A, const void *ws, hipStream_t st)
+hipError_t launch_refl3_sweep(const Refl3Plan &p, void *A, const void *ws, bool rev, hipStream_t st)
 {
     if (p.esize == 8 && p.band == refl3_band(8))
-        return sweep_launches<double, refl3_band(8)>(p, (double *)A, (const double *)ws, st);
+        return rev ? sweep_launches<double, refl3_band(8), true>(p, (double *)A, (const double *)ws, st)
+                   : sweep_launches<double, refl3_band(8), false>(p, (double *)A, (const double *)ws, st);
     if (p.esize == 4 && p.band == refl3_band(4))
-        return sweep_launches<float, refl3_band(4)>(p, (float *)A, (const float *)ws, st);
+        return rev ? sweep_launches<float, refl3_band(4), true>(p, (float *)A, (const float *)ws, st)
+                   : sweep_launches<float, refl3_band(4), false>(p, (float *)A, (const float *)ws, st);
     return hipErrorInvalidValue;
 }
 

@@ -266,3 +266,14 @@ def test_refl3_workspace_bytes():
     assert f32 >= 192 * 10240 * 5 * 4 and f32 < 192 * (10240 + 64) * 5 * 4 + 256
     assert f(b"d", 0, 100, 8) == 0 and f(b"d", 5, 2, 8) == 0 and f(b"d", 5, 100, 0) == 0
     assert f(b"x", 5, 100, 8) == 0
+
+
+def test_refl3_ex_workspace_bytes():
+    """Left application adds the packed copy; other options are refused."""
+    base = rs.refl3_workspace_bytes("float64", 300, 200, 24)
+    assert rs.refl3_workspace_bytes("float64", 300, 200, 24, {"inverse": 1}) == base
+    left = rs.refl3_workspace_bytes("float64", 300, 200, 24, {"left": 1})
+    right_t = rs.refl3_workspace_bytes("float64", 200, 300, 24)
+    assert left >= right_t + 300 * 200 * 8
+    assert rs.refl3_workspace_bytes("float64", 2, 200, 24, {"left": 1}) == 0
+    assert rs.refl3_workspace_bytes("float64", 300, 200, 24, {"band": 4}) == 0

@@ -130,3 +130,66 @@ def test_refl3_full_size_sampled_rows(dtype):
 def torch_index(rows):
     import torch
     return torch.as_tensor(rows, device="cuda")
+
+
+# Inverse order and application from the left (rotseq_refl3_ex_*): m x n, k,
+# lda padding; ragged tiles, one tile, three rows, several launches.
+SIDE_SHAPES = [(130, 37, 13, 3), (64, 64, 8, 0), (3, 70, 5, 1), (257, 260, 96, 5), (65, 9, 16, 1),
+               (40, 3, 20, 0)]
+
+
+def _side_problem(m, n, k, pa, left, seed):
+    """A (m x n, lda = m + pa) and reflectors over the mixed dimension."""
+    r = m if left else n
+    A = make_refl3_problem(m, n, 1, seed=seed, lda=m + pa).A
+    R = make_refl3_problem(1, r, k, seed=seed + 1)
+    return A, (R.TAU, R.NU1, R.NU2)
+
+
+@pytest.mark.parametrize("m,n,k,pa", SIDE_SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("inverse,left", [(True, False), (False, True), (True, True)])
+def test_refl3_inverse_and_left(m, n, k, pa, dtype, inverse, left):
+    import torch
+    say(f"refl3 {dtype} m={m} n={n} k={k} inverse={inverse} left={left}")
+    r = m if left else n
+    A0, coef = _side_problem(m, n, k, pa, left, seed=7 * m + n + k)
+    A = to_dev(A0, dtype)
+    dcoef = [to_dev(X, dtype) for X in coef]
+    pad = padding_bits(A)
+    rs.refl3seq(A, *dcoef, opts={"inverse": int(inverse), "left": int(left)})
+    torch.cuda.synchronize()
+    assert np.array_equal(pad, padding_bits(A)), "padding rows of A were modified"
+    ref = oracle.colmajor(widened(A0, dtype))
+    if r > 2:
+        oracle.refl3seq(ref, *(oracle.colmajor(widened(X, dtype)) for X in coef),
+                        inverse=inverse, left=left)
+    err = relerr(rs.host_colmajor(A), np.asarray(ref), A0)
+    say(f"  rel err {err:.3e}")
+    assert err <= TOL[dtype] * (10 if dtype == "f32" else 1)
+
+
+@pytest.mark.parametrize("left", [False, True])
+def test_refl3_inverse_undoes_forward(left):
+    """Orthogonal reflectors: the inverse call undoes a forward call."""
+    import torch
+    m, n, k = 150, 90, 21
+    r = m if left else n
+    rng = np.random.default_rng(3)
+    NU1, NU2 = rng.standard_normal((r - 2, k)), rng.standard_normal((r - 2, k))
+    TAU = 2.0 / (1.0 + NU1 ** 2 + NU2 ** 2)
+    A0 = make_refl3_problem(m, n, 1, seed=4).A
+    A = to_dev(A0, "f64")
+    dcoef = [to_dev(np.asfortranarray(X), "f64") for X in (TAU, NU1, NU2)]
+    rs.refl3seq(A, *dcoef, opts={"left": int(left)})
+    rs.refl3seq(A, *dcoef, opts={"left": int(left), "inverse": 1})
+    torch.cuda.synchronize()
+    assert relerr(rs.host_colmajor(A), np.asarray(A0), A0) <= 1e-13
+
+
+def test_refl3_ex_refuses_other_options():
+    A0, coef = _side_problem(70, 40, 8, 0, False, seed=9)
+    A = to_dev(A0, "f64")
+    dcoef = [to_dev(X, "f64") for X in coef]
+    with pytest.raises(rs.RotseqError):
+        rs.refl3seq(A, *dcoef, opts={"band": 4})
