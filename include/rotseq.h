@@ -251,8 +251,13 @@ int rotseq_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda,
  * in the device status word (rotseq_device_status) when one is not
  * orthogonal to within 64 eps; the call itself returns before that check
  * runs.
- * Only ROTSEQ_ARITH_AUTO / ROTSEQ_ARITH_LIFT are supported
- * (ROTSEQ_E_UNSUPPORTED otherwise).  Workspace as for rotseq_ex_d.
+ * ROTSEQ_ARITH_AUTO / ROTSEQ_ARITH_LIFT use that form (workspace as for
+ * rotseq_ex_d).  ROTSEQ_ARITH_EXACT applies the formula as written, so any
+ * (tau, nu) is accepted: the reflectors run on the 3x3 sweep as 3x3 ones
+ * with nu2 = 0 (workspace: rotseq_refl3_ex_workspace_bytes for the same m,
+ * n, k and `left`); forward order only, on either side (the inverse order,
+ * or any other field set, gives ROTSEQ_E_UNSUPPORTED).  ROTSEQ_ARITH_FMA is
+ * ROTSEQ_E_UNSUPPORTED.
  */
 int rotseq_refl_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda,
                      const double *TAU, int64_t ldt, const double *NU, int64_t ldn,

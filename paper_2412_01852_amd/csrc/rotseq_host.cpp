@@ -708,53 +708,27 @@ bool refl3_opts_ok(const rotseq_opts *o)
 // Workspace of a 3x3 reflector call: the records, then (left application)
 // the packed transposed copy.  False for shapes the sweep does not index.
 bool refl3_layout(Refl3Plan &p, size_t &off_pack, size_t &total, int64_t m, int64_t n, int64_t k,
-                  int64_t lda, int esize, bool left)
+                  int64_t lda, int esize, bool left, int width = 3)
 {
-    if (!refl3_plan(p, left ? n : m, left ? m : n, k, left ? n : lda, esize))
+    if (!refl3_plan(p, left ? n : m, left ? m : n, k, left ? n : lda, esize, width))
         return false;
     off_pack = (p.total + 255) & ~(size_t)255;
     total = left ? off_pack + (((size_t)m * (size_t)n * (size_t)esize + 255) & ~(size_t)255) : p.total;
     return true;
 }
 
+// The sweep of a call whose arguments are checked: reflectors `width`
+// columns wide (3; or 2 with NU2 == NULL), forward or inverse order, right
+// or left side.
 template <typename T>
-int run_refl3(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, int64_t ldt,
-              const T *NU1, int64_t ld1, const T *NU2, int64_t ld2, hipStream_t stream,
-              const rotseq_opts *opts, void *ws, size_t ws_bytes)
+int refl3_core(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, int64_t ldt,
+               const T *NU1, int64_t ld1, const T *NU2, int64_t ld2, int width, bool inverse,
+               bool left, hipStream_t stream, void *ws, size_t ws_bytes)
 {
-    const bool left = opts && opts->left, inverse = opts && opts->inverse;
-    const int64_t r = left ? m : n;  // the dimension the reflectors mix
-    if (m < 0)
-        return -1;
-    if (n < 0)
-        return -2;
-    if (k < 0)
-        return -3;
-    const bool work = (left ? n > 0 : m > 0) && r > 2 && k > 0;
-    const int64_t r2 = r > 2 ? r - 2 : 1;
-    if (work && A == nullptr)
-        return -4;
-    if (lda < (m > 1 ? m : 1))
-        return -5;
-    if (work && TAU == nullptr)
-        return -6;
-    if (ldt < r2)
-        return -7;
-    if (work && NU1 == nullptr)
-        return -8;
-    if (ld1 < r2)
-        return -9;
-    if (work && NU2 == nullptr)
-        return -10;
-    if (ld2 < r2)
-        return -11;
-    if (!refl3_opts_ok(opts))
-        return ROTSEQ_E_UNSUPPORTED;
-    if (!work)
-        return ROTSEQ_SUCCESS;
+    const int64_t r = left ? m : n;
     Refl3Plan p;
     size_t off_pack = 0, total = 0;
-    if (!refl3_layout(p, off_pack, total, m, n, k, lda, (int)sizeof(T), left))
+    if (!refl3_layout(p, off_pack, total, m, n, k, lda, (int)sizeof(T), left, width))
         return ROTSEQ_E_UNSUPPORTED;
     if (ws) {
         if (ws_bytes < total || ((uintptr_t)ws & 255) != 0)
@@ -801,6 +775,66 @@ int run_refl3(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, 
         profiler().finish(rec);
     }
     return ROTSEQ_SUCCESS;
+}
+
+template <typename T>
+int run_refl3(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, int64_t ldt,
+              const T *NU1, int64_t ld1, const T *NU2, int64_t ld2, hipStream_t stream,
+              const rotseq_opts *opts, void *ws, size_t ws_bytes)
+{
+    const bool left = opts && opts->left, inverse = opts && opts->inverse;
+    const int64_t r = left ? m : n;  // the dimension the reflectors mix
+    if (m < 0)
+        return -1;
+    if (n < 0)
+        return -2;
+    if (k < 0)
+        return -3;
+    const bool work = (left ? n > 0 : m > 0) && r > 2 && k > 0;
+    const int64_t r2 = r > 2 ? r - 2 : 1;
+    if (work && A == nullptr)
+        return -4;
+    if (lda < (m > 1 ? m : 1))
+        return -5;
+    if (work && TAU == nullptr)
+        return -6;
+    if (ldt < r2)
+        return -7;
+    if (work && NU1 == nullptr)
+        return -8;
+    if (ld1 < r2)
+        return -9;
+    if (work && NU2 == nullptr)
+        return -10;
+    if (ld2 < r2)
+        return -11;
+    if (!refl3_opts_ok(opts))
+        return ROTSEQ_E_UNSUPPORTED;
+    if (!work)
+        return ROTSEQ_SUCCESS;
+    return refl3_core(m, n, k, A, lda, TAU, ldt, NU1, ld1, NU2, ld2, 3, inverse, left, stream, ws,
+                      ws_bytes);
+}
+
+// 2x2 reflectors applied by the formula as written (ROTSEQ_ARITH_EXACT): any
+// (tau, nu), as 3x3 reflectors with nu2 = 0 on the 3x3 sweep.  Forward order
+// only (right, or left through the packed copy).
+template <typename T>
+int run_refl_exact(int64_t m, int64_t n, int64_t k, T *A, int64_t lda, const T *TAU, int64_t ldt,
+                   const T *NU, int64_t ldn, hipStream_t stream, const rotseq_opts *opts, void *ws,
+                   size_t ws_bytes)
+{
+    const bool left = opts->left != 0;
+    const int bad = check_args(m, n, k, A, lda, TAU, ldt, NU, ldn, left);
+    if (bad)
+        return bad;
+    if ((left ? n == 0 || m <= 1 : m == 0 || n <= 1) || k == 0)
+        return ROTSEQ_SUCCESS;
+    if (opts->inverse || opts->kernel != ROTSEQ_KERNEL_AUTO || opts->band || opts->waves ||
+        opts->publish || opts->shape)
+        return ROTSEQ_E_UNSUPPORTED;
+    return refl3_core<T>(m, n, k, A, lda, TAU, ldt, NU, ldn, nullptr, 0, 2, false, left, stream, ws,
+                         ws_bytes);
 }
 
 }  // namespace
@@ -873,6 +907,9 @@ int rotseq_refl_ex_d(int64_t m, int64_t n, int64_t k, double *A, int64_t lda, co
                      int64_t ldt, const double *NU, int64_t ldn, hipStream_t stream,
                      const rotseq_opts *opts, void *workspace, size_t ws_bytes)
 {
+    if (opts && opts->arith == ROTSEQ_ARITH_EXACT)
+        return run_refl_exact<double>(m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace,
+                                      ws_bytes);
     return run<double>(kReflect, m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace, ws_bytes);
 }
 
@@ -880,6 +917,9 @@ int rotseq_refl_ex_s(int64_t m, int64_t n, int64_t k, float *A, int64_t lda, con
                      int64_t ldt, const float *NU, int64_t ldn, hipStream_t stream,
                      const rotseq_opts *opts, void *workspace, size_t ws_bytes)
 {
+    if (opts && opts->arith == ROTSEQ_ARITH_EXACT)
+        return run_refl_exact<float>(m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace,
+                                     ws_bytes);
     return run<float>(kReflect, m, n, k, A, lda, TAU, ldt, NU, ldn, stream, opts, workspace, ws_bytes);
 }
 

@@ -15,11 +15,15 @@ struct Refl3Plan {
     int64_t m, n, k, lda;
     int esize, band, nbands, steps, waves;
     int64_t rec_elems;  // elements of the record buffer
+    int64_t nrefl;      // reflectors per sequence: n-2 (n-1 for 2x2 ones, nu2 = 0)
     size_t total;       // workspace bytes
 };
-// Fills `p` for a call with work (m > 0, n > 2, k > 0); false if the shape
-// is outside what the kernel indexes with 32-bit integers.  Host-only.
-bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int esize);
+// Fills `p` for a call with work (m > 0, n >= width, k > 0) of reflectors
+// `width` columns wide (3, or 2: 2x2 reflectors run as 3x3 ones with
+// nu2 = 0); false if the shape is outside what the kernel indexes with
+// 32-bit integers.  Host-only.
+bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int esize,
+                int width = 3);
 // cj: step between the records of reflectors j and j+1 in TAU, NU1, NU2
 // (1, or -1 with negative leading dimensions: the inverse order).
 hipError_t launch_refl3_prep(const Refl3Plan &p, const void *TAU, int64_t ldt, const void *NU1,

@@ -143,10 +143,14 @@ __device__ __forceinline__ void reflect3_dpp32(float &x, float &y, float &z, flo
 // zeros where that reflector does not exist (the sweep never applies those).
 // Reflector (j, p) is read at TAU[j*cj + p*ldt] (likewise NU1, NU2): cj = -1
 // with negative leading dimensions reads the reflectors in the inverse order.
+// Reflectors j < nrefl exist (n-2; n-1 for 2x2 reflectors, which run as 3x3
+// ones with NU2 == NULL, i.e. nu2 = 0: the third column of the last one
+// lies past A and is neither read into nor written by it).
 template <typename T>
 __global__ void refl3_prep(const T *__restrict__ TAU, int64_t ldt, const T *__restrict__ NU1,
-                           int64_t ld1, const T *__restrict__ NU2, int64_t ld2, int64_t cj, int64_t n,
-                           int64_t k, int K, int steps, int64_t total, T *__restrict__ rec)
+                           int64_t ld1, const T *__restrict__ NU2, int64_t ld2, int64_t cj,
+                           int64_t nrefl, int64_t k, int K, int steps, int64_t total,
+                           T *__restrict__ rec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total)
@@ -156,10 +160,10 @@ __global__ void refl3_prep(const T *__restrict__ TAU, int64_t ldt, const T *__re
     const int64_t t = r % steps, g = r / steps;
     const int64_t j = t - 2 * q, p = g * K + q;
     T tau = T(0), nu1 = T(0), nu2 = T(0);
-    if (j >= 0 && j < n - 2 && p < k) {
+    if (j >= 0 && j < nrefl && p < k) {
         tau = TAU[j * cj + p * ldt];
         nu1 = NU1[j * cj + p * ld1];
-        nu2 = NU2[j * cj + p * ld2];
+        nu2 = NU2 != nullptr ? NU2[j * cj + p * ld2] : T(0);
     }
     T *out = rec + kRec * i;
     out[0] = nu1;
@@ -392,9 +396,9 @@ hipError_t sweep_launches(const Refl3Plan &p, T *A, const T *rec, hipStream_t st
 
 }  // namespace
 
-bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int esize)
+bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int esize, int width)
 {
-    if (m <= 0 || n <= 2 || k <= 0 || m > INT32_MAX - kWave || n > INT32_MAX / 2)
+    if (m <= 0 || n < width || k <= 0 || m > INT32_MAX - kWave || n > INT32_MAX / 2)
         return false;
     p.m = m;
     p.n = n;
@@ -411,6 +415,7 @@ bool refl3_plan(Refl3Plan &p, int64_t m, int64_t n, int64_t k, int64_t lda, int 
     const int launches = (p.nbands + kRefl3MaxWaves - 1) / kRefl3MaxWaves;
     p.waves = (p.nbands + launches - 1) / launches;
     p.rec_elems = (int64_t)p.nbands * p.steps * p.band * kRec;
+    p.nrefl = n - width + 1;
     p.total = ((size_t)p.rec_elems * esize + 255) & ~(size_t)255;
     return true;
 }
@@ -424,11 +429,11 @@ hipError_t launch_refl3_prep(const Refl3Plan &p, const void *TAU, int64_t ldt, c
     const unsigned blocks = (unsigned)((total + B - 1) / B);
     if (p.esize == 8)
         refl3_prep<double><<<blocks, B, 0, st>>>((const double *)TAU, ldt, (const double *)NU1, ld1,
-                                                 (const double *)NU2, ld2, cj, p.n, p.k, p.band,
+                                                 (const double *)NU2, ld2, cj, p.nrefl, p.k, p.band,
                                                  p.steps, total, (double *)ws);
     else
         refl3_prep<float><<<blocks, B, 0, st>>>((const float *)TAU, ldt, (const float *)NU1, ld1,
-                                               (const float *)NU2, ld2, cj, p.n, p.k, p.band,
+                                               (const float *)NU2, ld2, cj, p.nrefl, p.k, p.band,
                                                p.steps, total, (float *)ws);
     return hipGetLastError();
 }

@@ -205,11 +205,14 @@ def test_left_argument_checks_without_device(fn):
     assert _ex(fn, 6, 3, 2, 1, 6, 1, 1, 1, 2) == -7
 
 
-def test_reflectors_need_lifting():
-    """Reflectors run only in the lifting form; other arithmetic is refused
-    before anything touches the device."""
-    for arith in (rs.ARITH_EXACT, rs.ARITH_FMA):
-        assert _ex("rotseq_refl_ex_d", 64, 10, 3, 1, 64, 1, 9, 1, 9, {"arith": arith}) == 4
+def test_reflectors_arithmetic():
+    """Reflectors run in the lifting form, or with ROTSEQ_ARITH_EXACT as written
+    (forward order only); the FMA form, and the inverse order or chain options
+    with the exact form, are refused before anything touches the device."""
+    assert _ex("rotseq_refl_ex_d", 64, 10, 3, 1, 64, 1, 9, 1, 9, {"arith": rs.ARITH_FMA}) == 4
+    for extra in ({"inverse": 1}, {"band": 4}, {"waves": 2}, {"kernel": rs.KERNEL_CHAIN}):
+        assert _ex("rotseq_refl_ex_d", 64, 10, 3, 1, 64, 1, 9, 1, 9,
+                   dict(extra, arith=rs.ARITH_EXACT)) == 4
 
 
 def test_left_workspace_adds_packed_copy():

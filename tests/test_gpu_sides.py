@@ -232,3 +232,39 @@ def test_refl_target_sampled_rows():
     oracle.reflseq(sub, oracle.colmajor(pb.C), oracle.colmajor(pb.S))
     got = rs.host_colmajor(A)[rows]
     assert relerr(got, np.asarray(sub), np.asarray(pb.A)[rows]) <= TOL["f64"]
+
+
+# General (non-orthogonal) 2x2 reflectors with ROTSEQ_ARITH_EXACT: the
+# formula as written, on the 3x3 sweep with nu2 = 0.
+@pytest.mark.parametrize("m,n,k,pa", [(130, 17, 33, 2), (64, 64, 8, 0), (1, 2, 1, 0), (200, 2, 9, 1),
+                                      (257, 300, 16, 3), (3, 129, 20, 0)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("left", [False, True])
+def test_refl_general_exact(m, n, k, pa, dtype, left):
+    say(f"general reflectors {dtype} m={m} n={n} k={k} left={left}")
+    pb = make_refl_problem(m, n, k, seed=29 * m + n + k, lda=m + pa, left=left)
+    rng = np.random.default_rng(m + n + k)
+    # tau (1 + nu^2) != 2; the factors' eigenvalues 1 and 1 - tau (1 + nu^2)
+    # stay in [0.8, 1], so A neither overflows nor vanishes over the sweep
+    TAU0 = oracle.colmajor(rng.uniform(0.0, 0.1, pb.C.shape))
+    NU0 = oracle.colmajor(rng.uniform(-1.0, 1.0, pb.S.shape))
+    A = to_dev(pb.A, dtype)
+    pad_before = padding_bits(A)
+    rs.reflseq(A, to_dev(TAU0, dtype), to_dev(NU0, dtype),
+               opts={"arith": rs.ARITH_EXACT, "left": int(left)})
+    _sync_ok()
+    assert np.array_equal(pad_before, padding_bits(A)), "padding rows of A were modified"
+    ref = oracle.colmajor(widened(pb.A, dtype))
+    oracle.reflseq(ref, oracle.colmajor(widened(TAU0, dtype)), oracle.colmajor(widened(NU0, dtype)),
+                   left=left)
+    ref = np.asarray(ref)
+    err = relerr(rs.host_colmajor(A), ref, ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= TOL[dtype] * 10
+
+
+def test_refl_general_exact_inverse_refused():
+    pb = make_refl_problem(70, 40, 8, seed=2)
+    A = to_dev(pb.A, "f64")
+    with pytest.raises(rs.RotseqError):
+        rs.reflseq(A, to_dev(pb.C, "f64"), to_dev(pb.S, "f64"), opts={"arith": rs.ARITH_EXACT, "inverse": 1})
