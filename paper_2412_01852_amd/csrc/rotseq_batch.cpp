@@ -24,7 +24,7 @@ size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
     items.clear();
     L.status_off = (size_t)count * sizeof(BatchItem);
     size_t off = a256(L.status_off + (size_t)count * sizeof(int));
-    int64_t o_neg = 0, o_par = 0, o_sign = 0, o_coef = 0, o_flags = 0;
+    int64_t o_neg = 0, o_par = 0, o_sign = 0, o_coef = 0, o_flags = 0, o_all = 0;
     for (int i = 0; i < count; ++i) {
         const BatchEntry &e = entries[i];
         BatchItem it{};
@@ -58,6 +58,9 @@ size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
         it.off_sign = o_sign;
         it.off_coef = o_coef;
         it.off_flags = o_flags;
+        it.off_all = o_all;
+        o_all += std::max<int64_t>(std::max<int64_t>((int64_t)it.npass * (it.steps + it.pad) * band, e.n),
+                                   (int64_t)it.tiles * it.npass);
         o_neg += (int64_t)it.npass * n1;
         o_par += n1;
         o_sign += e.n;
@@ -73,6 +76,7 @@ size_t batch_layout(const BatchEntry *entries, int count, int band, int esize,
     L.total_sign = o_sign;
     L.total_coef = o_coef;
     L.total_flags = o_flags;
+    L.total_all = o_all;
     return off;
 }
 

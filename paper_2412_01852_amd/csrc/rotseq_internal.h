@@ -79,6 +79,7 @@ struct BatchItem {
     int *flags;  // int[tiles * npass]
     int *status; // this item's error word (ROTSEQ_E_* bits of its waits)
     int64_t off_negmask, off_parity, off_sign, off_coef, off_flags, off_wg;
+    int64_t off_all;  // first index of the item in the coefficient/sign/flag stage
 };
 
 // Launch parameters shared by all items of a batch.
@@ -87,6 +88,7 @@ struct BatchLaunch {
     int esize, arith, band, waves, publish, spin_limit, wait_bias;
     size_t lds_bytes;
     int64_t total_negmask, total_parity, total_sign, total_coef, total_flags, nwg;
+    int64_t total_all;  // index space of the coefficient/sign/flag stage
     const BatchItem *items;  // device copy, `count` entries
     size_t status_off;       // byte offset of the items' error words in the block
 };

@@ -398,23 +398,20 @@ __global__ __launch_bounds__(256) void transpose_tiles(const T *__restrict__ src
 //
 // One launch per stage covers every problem of a batch: the stage's index
 // space is the concatenation of the problems' spaces, and each thread finds
-// its problem by binary search over the items' first indices.
+// its problem by binary search over the items' first indices.  Two stages,
+// as for a single call: the masks with their running parities (a thread
+// per pair), then everything else (a thread per coefficient record, final
+// sign or progress flag, whichever of the three is longest).
 
-enum BatchStage : int { kStageNegmask, kStageParity, kStageSign, kStageCoef, kStageFlags };
+enum BatchStage : int { kStageMasks, kStageAll };
 
 template <int STAGE>
 __device__ __forceinline__ int64_t stage_off(const BatchItem &it)
 {
-    if constexpr (STAGE == kStageNegmask)
-        return it.off_negmask;
-    else if constexpr (STAGE == kStageParity)
+    if constexpr (STAGE == kStageMasks)
         return it.off_parity;
-    else if constexpr (STAGE == kStageSign)
-        return it.off_sign;
-    else if constexpr (STAGE == kStageCoef)
-        return it.off_coef;
     else
-        return it.off_flags;
+        return it.off_all;
 }
 
 // Last item whose first index is <= idx (items are in ascending offset order).
@@ -453,21 +450,28 @@ __global__ void prep_batch(const BatchItem *__restrict__ items, int count, int64
     const BatchItem &it = items[item];
     const int64_t i = idx - stage_off<STAGE>(it);
     const int64_t n1 = it.n - 1;
-    if constexpr (STAGE == kStageNegmask) {
+    if constexpr (STAGE == kStageMasks) {
         bool unused = false;  // rotations only
-        it.negmask[i] = negmask_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1, it.k, K,
-                                     kRotate, i, unused);
+        unsigned acc = 0;
+        for (int pass = 0; pass < it.npass; ++pass) {
+            const int64_t e = (int64_t)pass * n1 + i;
+            const uint64_t nm = negmask_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1,
+                                             it.k, K, kRotate, e, unused);
+            it.negmask[e] = nm;
+            it.parity[e] = (uint8_t)acc;
+            acc ^= negmask_parities(nm);
+        }
+        it.parity[(int64_t)it.npass * n1 + i] = (uint8_t)acc;
+    } else {
+        if (i < (int64_t)it.tiles * it.npass)
+            it.flags[i] = 0;
+        if (arith == kLift && i < it.n)
+            ((T *)it.sign)[i] = sign_elem<T>(it.parity + (int64_t)it.npass * n1, it.n, i);
+        if (i < (int64_t)it.npass * (it.steps + it.pad) * K)
+            ((CoefPair<T> *)it.coef)[i] = coef_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds,
+                                                    n1, it.k, K, it.steps, it.pad, arith, kRotate,
+                                                    it.negmask, it.parity, i);
     }
-    else if constexpr (STAGE == kStageParity)
-        parity_elem(it.negmask, n1, it.npass, it.parity, i);
-    else if constexpr (STAGE == kStageSign)
-        ((T *)it.sign)[i] = sign_elem<T>(it.parity + (int64_t)it.npass * n1, it.n, i);
-    else if constexpr (STAGE == kStageCoef)
-        ((CoefPair<T> *)it.coef)[i] = coef_elem((const T *)it.C, 1, it.ldc, (const T *)it.S, it.lds, n1,
-                                                it.k, K, it.steps, it.pad, arith, kRotate, it.negmask,
-                                                it.parity, i);
-    else
-        it.flags[i] = 0;
 }
 
 inline unsigned blocks_for(int64_t count, int threads) { return (unsigned)((count + threads - 1) / threads); }
@@ -498,23 +502,12 @@ template <typename T>
 hipError_t prep_batch_t(const BatchLaunch &b, hipStream_t st)
 {
     constexpr int B = 256;
-    if (b.arith == kLift) {
-        if (b.total_negmask > 0)
-            prep_batch<T, kStageNegmask><<<blocks_for(b.total_negmask, B), B, 0, st>>>(
-                b.items, b.count, b.total_negmask, b.band, b.arith);
-        if (b.total_parity > 0)
-            prep_batch<T, kStageParity><<<blocks_for(b.total_parity, B), B, 0, st>>>(
-                b.items, b.count, b.total_parity, b.band, b.arith);
-        if (b.total_sign > 0)
-            prep_batch<T, kStageSign><<<blocks_for(b.total_sign, B), B, 0, st>>>(
-                b.items, b.count, b.total_sign, b.band, b.arith);
-    }
-    if (b.total_flags > 0)
-        prep_batch<T, kStageFlags><<<blocks_for(b.total_flags, B), B, 0, st>>>(
-            b.items, b.count, b.total_flags, b.band, b.arith);
-    if (b.total_coef > 0)
-        prep_batch<T, kStageCoef><<<blocks_for(b.total_coef, B), B, 0, st>>>(
-            b.items, b.count, b.total_coef, b.band, b.arith);
+    if (b.arith == kLift && b.total_parity > 0)
+        prep_batch<T, kStageMasks><<<blocks_for(b.total_parity, B), B, 0, st>>>(
+            b.items, b.count, b.total_parity, b.band, b.arith);
+    if (b.total_all > 0)
+        prep_batch<T, kStageAll><<<blocks_for(b.total_all, B), B, 0, st>>>(
+            b.items, b.count, b.total_all, b.band, b.arith);
     return hipGetLastError();
 }
 
