@@ -101,7 +101,8 @@ extern "C" {
  *   kernel  ROTSEQ_KERNEL_*
  *   band    sequences applied per wave per sweep over the columns
  *           (the paper's k_b, Section 2); 0 = auto.  MULTIPASS: 1, 2, 4,
- *           8 or 16; CHAIN: 4 or 8.
+ *           8 or 16; CHAIN: 2, 4, 6 or 8 (bands of 2 for single calls
+ *           only, not batches).
  *   waves   CHAIN only: waves (bands) per workgroup, 1..16; 0 = auto
  *           (sized so the workgroups match the CU count).
  *   publish CHAIN only: columns between progress updates across
