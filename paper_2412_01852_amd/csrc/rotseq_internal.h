@@ -150,7 +150,7 @@ int unroll_for_band(int band);
 // kChainDeepBands of them (the memory-bound regime of small k), with at most
 // kChainDeepWaves waves per workgroup.
 constexpr int kChainDeepBands = 4;
-constexpr int kChainDeepWaves = 4;
+constexpr int kChainDeepWaves = 8;
 int chain_unroll(int band, bool deep);
 size_t chain_lds_bytes(int band, int waves, int esize, bool deep = false);
 hipError_t chain_occupancy(int band, int arith, int esize, int waves, size_t lds, int *blocks,
