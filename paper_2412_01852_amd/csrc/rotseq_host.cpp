@@ -372,9 +372,16 @@ hipError_t configure_launch(Plan &p, int req_waves, int req_publish, int req_sha
         lds = chain_lds_bytes(p.band, waves, p.esize, p.deep != 0);
     } else {
         p.deep = stream ? 1 : 0;
+        const int64_t wgs4 = (total + 3) / 4;  // workgroups at 4 waves
+        const int deep_max = wgs4 >= (int64_t)(p.esize == 8 ? 2 : 4) * d.cus ? kChainDeepWaves : 4;
         double best = 1e300;
         for (int wv = 1; wv <= 16; ++wv) {
-            if (p.deep && (wv > kChainDeepWaves || wv % p.npass != 0))
+            // Streaming: 8 waves only where 4 would put several workgroups
+            // on every CU (at least 2 in FP64, 4 in FP32), else at most 4.
+            // Measured with 8: 65536 x 4096 FP64 k = 8 0.87 -> 0.81 ms, FP32
+            // 0.52 -> 0.48 ms; but 32768 x 4096 FP32 k = 8 0.30 -> 0.34 ms;
+            // the cost model below ties them.
+            if (p.deep && (wv > deep_max || wv % p.npass != 0))
                 continue;
             const size_t l = chain_lds_bytes(p.band, wv, p.esize, p.deep != 0);
             if (l > d.max_lds)
