@@ -107,15 +107,16 @@ CHAIN = [
 
 
 @pytest.mark.parametrize("band,k,waves", [(2, 8, 8), (4, 8, 8), (4, 16, 4), (8, 32, 8), (2, 3, 2)])
-def test_chain_streaming_fp64(band, k, waves):
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_chain_streaming(band, k, waves, dtype):
     """The streaming form (whole chains per workgroup: waves a multiple of
     the band count, at most 8) over ragged tiles and several tiles per
     workgroup, against the oracle."""
-    say(f"chain streaming fp64 band={band} k={k} waves={waves}")
+    say(f"chain streaming {dtype} band={band} k={k} waves={waves}")
     pb = make_problem(333, 211, k, seed=band * 10 + k, lda=340)
-    got, ref, pad_ok = run_full(pb, "f64", {"kernel": rs.KERNEL_CHAIN, "band": band, "waves": waves})
+    got, ref, pad_ok = run_full(pb, dtype, {"kernel": rs.KERNEL_CHAIN, "band": band, "waves": waves})
     assert pad_ok
-    assert relerr(got, ref, pb.A) <= TOL["f64"]
+    assert relerr(got, ref, widened(pb.A, dtype)) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("band,waves,publish", CHAIN)
